@@ -1,0 +1,200 @@
+/*
+ * pexsi_hip.h -- C ABI of the MI355X hot path of the PEXSI method
+ * (pole expansion and selected inversion, arXiv:1405.0194).
+ *
+ * What the library computes (paper, Sec. II.A-II.C):
+ *   for a real symmetric pencil (H, S), S positive definite, given on the
+ *   lower triangle of the union pattern of H and S,
+ *     - the pole table {z_l, omega_l^g} of eq. polerho / eq. gammaF,
+ *     - for each shift w_l = z_l + mu: a supernodal LDL^T factorization of
+ *       the complex symmetric A_l = H - w_l S (Sec. II.A "selected inversion"
+ *       and Sec. II.B steps 1-3), without pivoting,
+ *     - selected inversion: the entries of A_l^{-1} on the pattern of L
+ *       (Sec. II.B step 4),
+ *     - the pole sums Gamma^g = Im sum_l omega_l^g A_l^{-1} on the pattern
+ *       of H and S (eqs. gammapole, gammaF) and the traces Tr(Gamma^g S),
+ *       Tr(Gamma^g H) (eq. Nmu),
+ *     - inertia counts #{negative d_k} of H - eps S in real arithmetic
+ *       (Sec. II.C, Sylvester's law of inertia).
+ *
+ * Conventions
+ *   - Every function returns a pxs_status; nothing throws across the ABI.
+ *     Negative codes are usage/system errors and leave outputs untouched
+ *     unless stated.  PXS_TINY_PIVOT (> 0) is numeric: see info[].
+ *   - Host pointers are marked (host); device pointers (device) must be
+ *     device memory of the current HIP device.  The caller owns every array
+ *     passed in.  The library owns only the opaque handles and their host
+ *     metadata; it allocates no device memory on its own: the symbolic maps,
+ *     the factor storage and the workspace all live in caller buffers whose
+ *     sizes pxs_symbolic_info reports.
+ *   - Matrices are given as the lower triangle (row >= column, diagonal
+ *     included) in 0-based CSC: colptr (int64, n+1), rowind (int32, sorted
+ *     within each column).  Value arrays are aligned with rowind.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work on it and return without synchronising, except where an output
+ *     is a host array (traces, counts, info), which synchronises the stream.
+ *   - Complex numbers are pxs_c64 {re, im}, layout-compatible with C99
+ *     double complex and numpy/torch complex128.
+ */
+#ifndef PEXSI_HIP_H
+#define PEXSI_HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PXS_OK = 0,
+  PXS_EINVAL = -1,     /* bad argument (null pointer, size, malformed CSC) */
+  PXS_ENOMEM = -2,     /* host allocation failed */
+  PXS_EHIP = -3,       /* a HIP runtime call failed */
+  PXS_ESTATE = -4,     /* handle in the wrong state (e.g. maps not bound) */
+  PXS_TINY_PIVOT = 1   /* some |d_k| fell below the pivot threshold; info[] */
+} pxs_status;
+
+typedef struct { double re, im; } pxs_c64;
+
+typedef struct pxs_symbolic_s* pxs_symbolic;
+typedef struct pxs_numeric_s* pxs_numeric;
+
+/* Weight sets of the pole table, in this order (Sec. II.A, II.C). */
+enum { PXS_SET_RHO = 0, PXS_SET_E = 1, PXS_SET_F = 2, PXS_SET_D = 3 };
+
+typedef struct {
+  int32_t ordering;     /* 0: nested dissection (default), 1: natural order */
+  int32_t leaf_cols;    /* max columns of a nested-dissection leaf (0: 128) */
+  int32_t panel_width;  /* columns per numeric panel, 1..64 (0: 64) */
+  int32_t reserved0;
+  double pivot_tol;     /* |d_k| < pivot_tol * (max|H| + |w| max|S|) flags a
+                           tiny pivot (0: 1e-14) */
+  double reserved1[3];
+} pxs_options;
+
+typedef struct {
+  int64_t n;                   /* matrix dimension */
+  int64_t nnz_lower;           /* entries of the lower input pattern */
+  int64_t nnz_L;               /* stored entries of L (supernodal, incl. the
+                                  dense diagonal blocks' lower triangles) */
+  int64_t nnz_L_exact;         /* entries of the exact pattern of L */
+  int64_t nsuper;              /* supernodes */
+  int64_t npanel;              /* numeric panels (supernodes cut into
+                                  panel_width-wide column blocks) */
+  int64_t bytes_per_shift;     /* factor storage per complex shift (bytes);
+                                  a real (inertia) shift needs half */
+  int64_t work_bytes;          /* workspace for a batch of nshift shifts:
+                                  work_fixed + nshift * work_per_shift */
+  int64_t work_fixed;
+  int64_t work_per_shift;
+  int64_t map_bytes;           /* device bytes of the symbolic maps */
+  int64_t max_front;           /* largest row count of a supernode */
+  double flops_factor;         /* algorithmic flops per complex shift:
+                                  8 * sum_k c_k (c_k + 1) / 2 */
+  double flops_selinv;         /* 8 * sum_k (c_k^2 + c_k) */
+  /* c_k = off-diagonal nonzeros of column k in the exact pattern of L */
+} pxs_syminfo;
+
+/* ---------------------------------------------------------------------- */
+/* Pole table (Sec. II.A, eq. polerho; eq. gammaF; Sec. II.C).
+ * beta: inverse temperature (1/Ha); dE: bound on max|eps - mu| over the
+ * pencil's spectrum; mu: chemical potential; P: number of poles (even, >= 2).
+ * Out (host): shifts[P] = z_l + mu (all with positive imaginary part) and
+ * weights[nsets * P] (set-major: weights[g * P + l]) for the first nsets of
+ * {rho, E, F, d}, 1 <= nsets <= 4, such that
+ *   g(eps - mu) ~= Im sum_l weights[g*P+l] / (eps - shifts[l]).
+ * Errors: PXS_EINVAL for P odd or < 2, beta/dE <= 0, nsets out of range. */
+pxs_status pxs_poles(double beta, double dE, double mu, int32_t P, int32_t nsets,
+                     pxs_c64* shifts, pxs_c64* weights);
+
+/* ---------------------------------------------------------------------- */
+/* Symbolic analysis (Sec. II.B steps 1-2; eq. parent).  Host only.
+ * n, colptr, rowind (host): lower CSC of the union pattern of H and S.
+ * nblk, blkptr (host, nullable): atom blocks, blkptr[0]=0 .. blkptr[nblk]=n;
+ *   columns of a block stay together and are treated as one graph vertex.
+ *   NULL: every column is its own block.
+ * coords (host, nullable): nblk x 3 block positions, used for geometric
+ *   nested dissection; NULL: graph (level-structure) nested dissection.
+ * opt (host, nullable): NULL = defaults.
+ * Out: *out, an immutable handle; free with pxs_free_symbolic.
+ * Errors: PXS_EINVAL for a malformed pattern (unsorted or upper entries,
+ *   missing diagonal, bad blkptr), PXS_ENOMEM. */
+pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind,
+                       int32_t nblk, const int32_t* blkptr, const double* coords,
+                       const pxs_options* opt, pxs_symbolic* out);
+
+pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info);
+
+/* Export of the analysis, for tests and tools (host arrays, any may be NULL):
+ * perm[n] (new -> old column), super_ptr[nsuper+1] (first new column of each
+ * supernode), super_parent[nsuper] (-1 for roots), row_ptr[nsuper+1] and
+ * rows[row_ptr[nsuper]] (the sorted new row indices of each supernode, its
+ * own columns first). */
+pxs_status pxs_symbolic_export(pxs_symbolic sym, int32_t* perm, int32_t* super_ptr,
+                               int32_t* super_parent, int64_t* row_ptr, int32_t* rows);
+
+/* Copies the symbolic maps into `maps` (device, info.map_bytes bytes,
+ * 256-byte aligned) on `stream` and records that buffer in the handle.
+ * Must precede any numeric call; the buffer must outlive the handle's use. */
+pxs_status pxs_symbolic_bind(pxs_symbolic sym, void* maps, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Numeric LDL^T of A_l = H - shifts[l] S for l < nshift (Sec. II.B step 3):
+ * assembles every shift into Lbuf and factors it in place.
+ * Hval, Sval (device, nnz_lower doubles): values on the input pattern.
+ * shifts (host, nshift): complex shifts w_l; Im w_l > 0 guarantees that
+ *   the factorization exists (Im A_l is negative definite).
+ * Lbuf (device, nshift * bytes_per_shift), work (device, work_fixed +
+ *   nshift * work_per_shift): caller buffers, kept by the numeric handle.
+ * info (host, nshift, nullable): 0, or the 1-based new column index of the
+ *   first pivot below the threshold (the factor continues regardless).
+ * Returns PXS_TINY_PIVOT if any info[l] != 0 (then synchronises stream). */
+pxs_status pxs_factor(pxs_symbolic sym, const double* Hval, const double* Sval,
+                      int32_t nshift, const pxs_c64* shifts, void* Lbuf, void* work,
+                      int64_t* info, void* stream, pxs_numeric* out);
+
+/* Selected inversion in place (Sec. II.B step 4): afterwards Lbuf holds
+ * Z_l = A_l^{-1} on the (supernodal) pattern of L for every shift. */
+pxs_status pxs_selinv(pxs_numeric num, void* stream);
+
+/* Pole sums (eqs. gammapole, gammaF): for every input entry k and set g < nsets,
+ * out[g * nnz_lower + k] = Im sum_l weights[g * nshift + l] * Z_l[k]
+ * (device output, input ordering).  traces (host, 2 * nsets, nullable):
+ * traces[2g] = Tr(Gamma^g S), traces[2g+1] = Tr(Gamma^g H) over the full
+ * symmetric matrices.  Requires pxs_selinv first. */
+pxs_status pxs_pole_sum(pxs_numeric num, int32_t nsets, const pxs_c64* weights,
+                        double* out, double* traces, void* stream);
+
+/* Z_l on the input pattern (device out[nnz_lower], input ordering). */
+pxs_status pxs_get_selected(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream);
+
+/* D of shift l after pxs_factor (device out[n], new ordering). */
+pxs_status pxs_get_diag(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream);
+
+/* Inertia counts (Sec. II.C): real LDL^T of H - eps[q] S for q < nshift and
+ * neg_count[q] = #{k : d_k < 0} (host).  Lbuf needs nshift * bytes_per_shift
+ * / 2 bytes, work as for pxs_factor.  info as for pxs_factor: a tiny pivot
+ * makes the count unreliable; shift eps slightly and retry.  Synchronises. */
+pxs_status pxs_inertia(pxs_symbolic sym, const double* Hval, const double* Sval,
+                       int32_t nshift, const double* eps, void* Lbuf, void* work,
+                       int64_t* neg_count, int64_t* info, void* stream);
+
+/* Fused: poles + factor + selinv + pole sums, with the buffers above;
+ * shifts/weights (host, nullable) receive the pole table used. */
+pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double* Sval,
+                              double beta, double dE, double mu, int32_t P, int32_t nsets,
+                              void* Lbuf, void* work, double* out, double* traces,
+                              int64_t* info, pxs_c64* shifts, pxs_c64* weights,
+                              void* stream);
+
+/* Text of the last HIP or validation error seen by this thread (diagnostics). */
+const char* pxs_last_error(void);
+
+void pxs_free_symbolic(pxs_symbolic sym);
+void pxs_free_numeric(pxs_numeric num);
+const char* pxs_status_string(pxs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PEXSI_HIP_H */

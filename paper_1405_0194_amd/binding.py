@@ -1,0 +1,294 @@
+"""Thin ctypes binding of libpexsi_hip.so (include/pexsi_hip.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch provides device memory (the caller-owned buffers of the
+C ABI) and the current HIP stream.  There is no fallback: if the compiled
+library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpexsi_hip.so")
+
+PXS_OK, PXS_EINVAL, PXS_ENOMEM, PXS_EHIP, PXS_ESTATE, PXS_TINY_PIVOT = 0, -1, -2, -3, -4, 1
+SETS = ("rho", "E", "F", "d")
+
+
+class PxsError(RuntimeError):
+    def __init__(self, fn, code, detail=""):
+        self.code = code
+        super().__init__(f"{fn} failed with status {code}: {detail}")
+
+
+class c64(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("ordering", C.c_int32), ("leaf_cols", C.c_int32), ("panel_width", C.c_int32),
+                ("reserved0", C.c_int32), ("pivot_tol", C.c_double), ("reserved1", C.c_double * 3)]
+
+
+class SymInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz_lower", C.c_int64), ("nnz_L", C.c_int64),
+                ("nnz_L_exact", C.c_int64), ("nsuper", C.c_int64), ("npanel", C.c_int64),
+                ("bytes_per_shift", C.c_int64), ("work_bytes", C.c_int64),
+                ("work_fixed", C.c_int64), ("work_per_shift", C.c_int64),
+                ("map_bytes", C.c_int64), ("max_front", C.c_int64),
+                ("flops_factor", C.c_double), ("flops_selinv", C.c_double)]
+
+
+_P = C.c_void_p
+_lib = None
+
+
+def load():
+    """Loads the compiled library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    sig = {
+        "pxs_poles": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, _P, _P]),
+        "pxs_analyze": (C.c_int, [C.c_int32, _P, _P, C.c_int32, _P, _P, _P, _P]),
+        "pxs_symbolic_info": (C.c_int, [_P, _P]),
+        "pxs_symbolic_export": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+        "pxs_symbolic_bind": (C.c_int, [_P, _P, _P]),
+        "pxs_factor": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+        "pxs_selinv": (C.c_int, [_P, _P]),
+        "pxs_pole_sum": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P]),
+        "pxs_get_selected": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "pxs_get_diag": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "pxs_inertia": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+        "pxs_density_matrix": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                         C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
+        "pxs_free_symbolic": (None, [_P]),
+        "pxs_free_numeric": (None, [_P]),
+        "pxs_status_string": (C.c_char_p, [C.c_int]),
+        "pxs_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(fn, code, allow=(PXS_OK,)):
+    if code not in allow:
+        lib = load()
+        detail = lib.pxs_status_string(code).decode()
+        extra = lib.pxs_last_error().decode()
+        raise PxsError(fn, code, detail + (f" ({extra})" if extra else ""))
+    return code
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_P)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return _P(s.cuda_stream)
+
+
+def _dptr(t):
+    return _P(t.data_ptr())
+
+
+# --------------------------------------------------------------------------
+def poles(beta: float, dE: float, mu: float, P: int, nsets: int = 2):
+    """Pole table from the library: shifts (P,) complex, weights (nsets, P)."""
+    lib = load()
+    sh = np.zeros(P, dtype=np.complex128)
+    wt = np.zeros(nsets * P, dtype=np.complex128)
+    _check("pxs_poles", lib.pxs_poles(beta, dE, mu, P, nsets, _ptr(sh), _ptr(wt)))
+    return sh, wt.reshape(nsets, P)
+
+
+class Analysis:
+    """Symbolic analysis handle (host), optionally bound to device maps."""
+
+    def __init__(self, n, colptr, rowind, blkptr=None, coords=None, ordering=0, leaf_cols=0,
+                 panel_width=0, pivot_tol=0.0):
+        lib = load()
+        self._lib = lib
+        self.n = int(n)
+        colptr = np.ascontiguousarray(colptr, dtype=np.int64)
+        rowind = np.ascontiguousarray(rowind, dtype=np.int32)
+        opt = Options(ordering, leaf_cols, panel_width, 0, pivot_tol)
+        h = _P()
+        nblk = 0
+        bp = None
+        cp = None
+        if blkptr is not None:
+            blkptr = np.ascontiguousarray(blkptr, dtype=np.int32)
+            nblk = blkptr.shape[0] - 1
+            bp = _ptr(blkptr)
+        if coords is not None:
+            coords = np.ascontiguousarray(coords, dtype=np.float64)
+            if blkptr is None:
+                nblk = coords.shape[0]
+            cp = _ptr(coords)
+        _check("pxs_analyze", lib.pxs_analyze(self.n, _ptr(colptr), _ptr(rowind), nblk, bp, cp,
+                                               C.byref(opt), C.byref(h)))
+        self._h = h
+        info = SymInfo()
+        _check("pxs_symbolic_info", lib.pxs_symbolic_info(h, C.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in SymInfo._fields_}
+        self.maps = None
+
+    @classmethod
+    def from_system(cls, system, **kw):
+        return cls(system.n, system.colptr, system.rowind, blkptr=system.blkptr,
+                   coords=system.coords, **kw)
+
+    def export(self):
+        i = self.info
+        ns = i["nsuper"]
+        perm = np.zeros(self.n, dtype=np.int32)
+        sp = np.zeros(ns + 1, dtype=np.int32)
+        par = np.zeros(ns, dtype=np.int32)
+        rp = np.zeros(ns + 1, dtype=np.int64)
+        _check("pxs_symbolic_export", self._lib.pxs_symbolic_export(self._h, _ptr(perm), _ptr(sp), _ptr(par),
+                                                                     _ptr(rp), None))
+        rows = np.zeros(int(rp[-1]), dtype=np.int32)
+        _check("pxs_symbolic_export", self._lib.pxs_symbolic_export(self._h, None, None, None, None,
+                                                                     _ptr(rows)))
+        return dict(perm=perm, super_ptr=sp, parent=par, row_ptr=rp, rows=rows)
+
+    def bind(self, device="cuda"):
+        import torch
+        if self.maps is None:
+            self.maps = torch.empty(self.info["map_bytes"], dtype=torch.uint8, device=device)
+            _check("pxs_symbolic_bind", self._lib.pxs_symbolic_bind(self._h, _dptr(self.maps), _stream()))
+        return self
+
+    def buffers(self, nshift, real=False, device="cuda"):
+        """Allocates (Lbuf, work) device buffers for a batch of nshift shifts."""
+        import torch
+        per = self.info["bytes_per_shift"] // (2 if real else 1)
+        L = torch.empty(per * nshift, dtype=torch.uint8, device=device)
+        W = torch.empty(self.info["work_fixed"] + nshift * self.info["work_per_shift"],
+                        dtype=torch.uint8, device=device)
+        return L, W
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                self._lib.pxs_free_symbolic(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Factorization:
+    """A batch of shifts factored (and optionally inverted) in caller buffers."""
+
+    def __init__(self, analysis: Analysis, H, S, shifts, L=None, work=None, stream=None):
+        lib = load()
+        self._lib = lib
+        self.analysis = analysis
+        analysis.bind()
+        self.shifts = np.ascontiguousarray(shifts, dtype=np.complex128)
+        nshift = self.shifts.shape[0]
+        self.nshift = nshift
+        if L is None or work is None:
+            L, work = analysis.buffers(nshift)
+        self.L, self.work = L, work
+        self.H, self.S = H, S   # keep the device value arrays alive
+        self.info = np.zeros(nshift, dtype=np.int64)
+        h = _P()
+        code = lib.pxs_factor(analysis._h, _dptr(H), _dptr(S), nshift, _ptr(self.shifts),
+                              _dptr(L), _dptr(work), _ptr(self.info), _stream(stream), C.byref(h))
+        _check("pxs_factor", code, allow=(PXS_OK, PXS_TINY_PIVOT))
+        self._h = h
+        self.inverted = False
+
+    def diag(self, l, stream=None):
+        import torch
+        out = torch.empty(self.analysis.n, dtype=torch.complex128, device=self.L.device)
+        _check("pxs_get_diag", self._lib.pxs_get_diag(self._h, l, _dptr(out), _stream(stream)))
+        return out
+
+    def selinv(self, stream=None):
+        _check("pxs_selinv", self._lib.pxs_selinv(self._h, _stream(stream)))
+        self.inverted = True
+        return self
+
+    def selected(self, l, stream=None):
+        """Z_l on the input pattern (complex128 tensor, input ordering)."""
+        import torch
+        out = torch.empty(self.analysis.info["nnz_lower"], dtype=torch.complex128, device=self.L.device)
+        _check("pxs_get_selected", self._lib.pxs_get_selected(self._h, l, _dptr(out), _stream(stream)))
+        return out
+
+    def pole_sum(self, weights, stream=None, out=None):
+        """weights: (nsets, nshift) complex.  Returns (out (nsets, nnz), traces
+        array (nsets, 2) = [Tr(G S), Tr(G H)])."""
+        import torch
+        weights = np.ascontiguousarray(weights, dtype=np.complex128)
+        nsets = weights.shape[0]
+        nnz = self.analysis.info["nnz_lower"]
+        if out is None:
+            out = torch.empty(nsets * nnz, dtype=torch.float64, device=self.L.device)
+        tr = np.zeros(2 * nsets)
+        _check("pxs_pole_sum", self._lib.pxs_pole_sum(self._h, nsets, _ptr(weights), _dptr(out), _ptr(tr),
+                                                       _stream(stream)))
+        return out.view(nsets, nnz), tr.reshape(nsets, 2)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                self._lib.pxs_free_numeric(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def inertia(analysis: Analysis, H, S, eps, L=None, work=None, stream=None):
+    """Counts #{k : d_k < 0} of H - eps_q S for each q (host int64 array) and
+    the per-shift tiny-pivot info."""
+    lib = load()
+    analysis.bind()
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    q = eps.shape[0]
+    if L is None or work is None:
+        L, work = analysis.buffers(q, real=True)
+    neg = np.zeros(q, dtype=np.int64)
+    info = np.zeros(q, dtype=np.int64)
+    code = lib.pxs_inertia(analysis._h, _dptr(H), _dptr(S), q, _ptr(eps), _dptr(L), _dptr(work),
+                           _ptr(neg), _ptr(info), _stream(stream))
+    _check("pxs_inertia", code, allow=(PXS_OK, PXS_TINY_PIVOT))
+    return neg, info
+
+
+def density_matrix(analysis: Analysis, H, S, beta, dE, mu, P, nsets=2, L=None, work=None,
+                   stream=None):
+    """Fused poles + factor + selinv + pole sums.  Returns (out (nsets, nnz)
+    tensor, traces (nsets, 2), info, shifts, weights)."""
+    import torch
+    lib = load()
+    analysis.bind()
+    if L is None or work is None:
+        L, work = analysis.buffers(P)
+    nnz = analysis.info["nnz_lower"]
+    out = torch.empty(nsets * nnz, dtype=torch.float64, device=L.device)
+    tr = np.zeros(2 * nsets)
+    info = np.zeros(P, dtype=np.int64)
+    sh = np.zeros(P, dtype=np.complex128)
+    wt = np.zeros(nsets * P, dtype=np.complex128)
+    code = lib.pxs_density_matrix(analysis._h, _dptr(H), _dptr(S), beta, dE, mu, P, nsets, _dptr(L),
+                                  _dptr(work), _dptr(out), _ptr(tr), _ptr(info), _ptr(sh), _ptr(wt),
+                                  _stream(stream))
+    _check("pxs_density_matrix", code, allow=(PXS_OK, PXS_TINY_PIVOT))
+    return out.view(nsets, nnz), tr.reshape(nsets, 2), info, sh, wt.reshape(nsets, P)

@@ -1,0 +1,321 @@
+// C ABI (include/pexsi_hip.h): argument checking, handle management and the
+// sequencing of the numeric phases.  No device memory is allocated here: the
+// maps, factor storage and workspace are caller buffers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pexsi_hip.h"
+#include "numeric.h"
+#include "pxs_internal.h"
+
+struct pxs_symbolic_s {
+  pxs::Symbolic S;
+};
+
+struct pxs_numeric_s {
+  const pxs::Symbolic* S = nullptr;
+  const double* H = nullptr;
+  const double* Sv = nullptr;
+  int32_t nshift = 0;
+  std::vector<double> shifts;   // 2 per shift (host copy, source of the async upload)
+  std::vector<double> weights;  // host staging for pole sums
+  void* L = nullptr;
+  void* work = nullptr;
+  bool selinv_done = false;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+pxs_status hip_fail(int e) {
+  g_last_error = hipGetErrorString((hipError_t)e);
+  return PXS_EHIP;
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+template <class T>
+void append_bytes(std::vector<char>& buf, int64_t& off, const std::vector<T>& v) {
+  off = (int64_t)((buf.size() + 255) / 256 * 256);
+  buf.resize(off + v.size() * sizeof(T));
+  if (!v.empty()) std::memcpy(buf.data() + off, v.data(), v.size() * sizeof(T));
+}
+
+// Packs the device maps of a symbolic handle; also fills S.map_bytes and the
+// offsets (deterministic, so info and bind agree).
+void pack_maps(pxs::Symbolic& S, std::vector<char>* out) {
+  std::vector<char> buf;
+  if (S.diagoff.empty()) {
+    S.diagoff.resize(S.n);
+    for (int32_t J = 0; J < S.nsuper; ++J)
+      for (int32_t c = S.sfirst[J]; c < S.sfirst[J + 1]; ++c) {
+        const int64_t q = c - S.sfirst[J];
+        S.diagoff[c] = S.off[J] + q * S.ld[J] + q;
+      }
+  }
+  append_bytes(buf, S.o_colmap, S.colmap);
+  append_bytes(buf, S.o_colseg, S.colseg);
+  append_bytes(buf, S.o_entry_off, S.entry_off);
+  append_bytes(buf, S.o_diagoff, S.diagoff);
+  append_bytes(buf, S.o_relpos, S.relpos);
+  append_bytes(buf, S.o_entry_diag, S.entry_diag);
+  S.map_bytes = (int64_t)((buf.size() + 255) / 256 * 256);
+  if (out) out->swap(buf);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pxs_status_string(pxs_status s) {
+  switch (s) {
+    case PXS_OK: return "ok";
+    case PXS_EINVAL: return "invalid argument";
+    case PXS_ENOMEM: return "out of host memory";
+    case PXS_EHIP: return "HIP runtime error";
+    case PXS_ESTATE: return "handle in the wrong state";
+    case PXS_TINY_PIVOT: return "tiny pivot (see info)";
+  }
+  return "unknown status";
+}
+
+const char* pxs_last_error(void) { return g_last_error.c_str(); }
+
+pxs_status pxs_poles(double beta, double dE, double mu, int32_t P, int32_t nsets, pxs_c64* shifts,
+                     pxs_c64* weights) {
+  if (!shifts || !weights) return PXS_EINVAL;
+  if (pxs::pole_table(beta, dE, mu, P, nsets, (double*)shifts, (double*)weights) != 0) return PXS_EINVAL;
+  return PXS_OK;
+}
+
+pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nblk,
+                       const int32_t* blkptr, const double* coords, const pxs_options* opt,
+                       pxs_symbolic* out) {
+  if (!out || !colptr || !rowind || n <= 0) return PXS_EINVAL;
+  *out = nullptr;
+  pxs::AnalyzeOptions o;
+  if (opt) {
+    o.ordering = opt->ordering;
+    if (opt->leaf_cols > 0) o.leaf_cols = opt->leaf_cols;
+    if (opt->panel_width > 0) o.panel_width = opt->panel_width;
+    if (opt->pivot_tol > 0) o.pivot_tol = opt->pivot_tol;
+    if (o.ordering != 0 && o.ordering != 1) return PXS_EINVAL;
+    if (o.panel_width > 64) return PXS_EINVAL;
+  }
+  pxs_symbolic_s* h = new (std::nothrow) pxs_symbolic_s;
+  if (!h) return PXS_ENOMEM;
+  std::string msg;
+  try {
+    if (pxs::analyze(n, colptr, rowind, nblk, blkptr, coords, o, h->S, msg) != 0) {
+      g_last_error = msg;
+      delete h;
+      return PXS_EINVAL;
+    }
+    h->S.work_fixed = pxs::WK_FIXED_BYTES;
+    pack_maps(h->S, nullptr);
+  } catch (const std::bad_alloc&) {
+    delete h;
+    return PXS_ENOMEM;
+  }
+  *out = h;
+  return PXS_OK;
+}
+
+pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info) {
+  if (!sym || !info) return PXS_EINVAL;
+  const pxs::Symbolic& S = sym->S;
+  std::memset(info, 0, sizeof(*info));
+  info->n = S.n;
+  info->nnz_lower = S.nnz_lower;
+  info->nnz_L = S.nnzL_stored_lower;
+  info->nnz_L_exact = S.nnzL_exact;
+  info->nsuper = S.nsuper;
+  info->npanel = (int64_t)S.panels.size();
+  info->bytes_per_shift = 16 * S.nnzL_store;
+  info->work_fixed = S.work_fixed;
+  info->work_per_shift = S.work_per_shift;
+  info->work_bytes = S.work_fixed + S.work_per_shift;
+  info->map_bytes = S.map_bytes;
+  info->max_front = S.max_front;
+  info->flops_factor = S.flops_factor;
+  info->flops_selinv = S.flops_selinv;
+  return PXS_OK;
+}
+
+pxs_status pxs_symbolic_export(pxs_symbolic sym, int32_t* perm, int32_t* super_ptr,
+                               int32_t* super_parent, int64_t* row_ptr, int32_t* rows) {
+  if (!sym) return PXS_EINVAL;
+  const pxs::Symbolic& S = sym->S;
+  if (perm) std::memcpy(perm, S.perm.data(), sizeof(int32_t) * S.n);
+  if (super_ptr) std::memcpy(super_ptr, S.sfirst.data(), sizeof(int32_t) * (S.nsuper + 1));
+  if (super_parent) std::memcpy(super_parent, S.sparent.data(), sizeof(int32_t) * S.nsuper);
+  if (row_ptr) std::memcpy(row_ptr, S.rowptr.data(), sizeof(int64_t) * (S.nsuper + 1));
+  if (rows) std::memcpy(rows, S.rows.data(), sizeof(int32_t) * S.rows.size());
+  return PXS_OK;
+}
+
+pxs_status pxs_symbolic_bind(pxs_symbolic sym, void* maps, void* stream) {
+  if (!sym || !maps || !aligned256(maps)) return PXS_EINVAL;
+  std::vector<char> buf;
+  try {
+    pack_maps(sym->S, &buf);
+  } catch (const std::bad_alloc&) {
+    return PXS_ENOMEM;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(maps, buf.data(), buf.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return hip_fail(e);
+  // the host staging buffer dies here: wait for the copy
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e);
+  sym->S.dmaps = maps;
+  return PXS_OK;
+}
+
+static pxs_status check_numeric_args(pxs_symbolic sym, const double* H, const double* Sv, int32_t nshift,
+                                     void* Lbuf, void* work) {
+  if (!sym || !H || !Sv || !Lbuf || !work) return PXS_EINVAL;
+  if (nshift < 1 || nshift > pxs::MAX_SHIFTS) return PXS_EINVAL;
+  if (!aligned256(Lbuf) || !aligned256(work)) return PXS_EINVAL;
+  if (!sym->S.dmaps) return PXS_ESTATE;
+  return PXS_OK;
+}
+
+pxs_status pxs_factor(pxs_symbolic sym, const double* Hval, const double* Sval, int32_t nshift,
+                      const pxs_c64* shifts, void* Lbuf, void* work, int64_t* info, void* stream,
+                      pxs_numeric* out) {
+  pxs_status s0 = check_numeric_args(sym, Hval, Sval, nshift, Lbuf, work);
+  if (s0 != PXS_OK) return s0;
+  if (!shifts || !out) return PXS_EINVAL;
+  for (int32_t l = 0; l < nshift; ++l)
+    if (!std::isfinite(shifts[l].re) || !std::isfinite(shifts[l].im)) return PXS_EINVAL;
+  pxs_numeric_s* h = new (std::nothrow) pxs_numeric_s;
+  if (!h) return PXS_ENOMEM;
+  h->S = &sym->S;
+  h->H = Hval;
+  h->Sv = Sval;
+  h->nshift = nshift;
+  h->shifts.assign((const double*)shifts, (const double*)shifts + 2 * nshift);
+  h->L = Lbuf;
+  h->work = work;
+  hipStream_t st = (hipStream_t)stream;
+  int e = pxs::run_factor<true>(sym->S, Hval, Sval, nshift, h->shifts.data(), Lbuf, work, st);
+  if (e != 0) {
+    delete h;
+    return hip_fail(e);
+  }
+  *out = h;
+  if (info) {
+    hipError_t he = hipMemcpyAsync(info, (char*)work + pxs::WK_INFO, sizeof(int64_t) * nshift,
+                                   hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(he);
+    for (int32_t l = 0; l < nshift; ++l)
+      if (info[l] != 0) return PXS_TINY_PIVOT;
+  }
+  return PXS_OK;
+}
+
+pxs_status pxs_selinv(pxs_numeric num, void* stream) {
+  if (!num) return PXS_EINVAL;
+  if (num->selinv_done) return PXS_ESTATE;
+  int e = pxs::run_selinv(*num->S, num->nshift, num->L, num->work, (hipStream_t)stream);
+  if (e != 0) return hip_fail(e);
+  num->selinv_done = true;
+  return PXS_OK;
+}
+
+pxs_status pxs_pole_sum(pxs_numeric num, int32_t nsets, const pxs_c64* weights, double* out,
+                        double* traces, void* stream) {
+  if (!num || !weights || !out || nsets < 1 || nsets > 4) return PXS_EINVAL;
+  if (!num->selinv_done) return PXS_ESTATE;
+  num->weights.assign((const double*)weights, (const double*)weights + 2 * nsets * num->nshift);
+  hipStream_t st = (hipStream_t)stream;
+  int e = pxs::run_pole_sum(*num->S, num->nshift, num->L, num->work, num->H, num->Sv, nsets,
+                            num->weights.data(), out, st);
+  if (e != 0) return hip_fail(e);
+  if (traces) {
+    double t8[8];
+    hipError_t he = hipMemcpyAsync(t8, (char*)num->work + pxs::WK_TRACES, sizeof(t8),
+                                   hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(he);
+    for (int g = 0; g < 2 * nsets; ++g) traces[g] = t8[g];
+  }
+  return PXS_OK;
+}
+
+pxs_status pxs_get_selected(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream) {
+  if (!num || !out || shift < 0 || shift >= num->nshift) return PXS_EINVAL;
+  int e = pxs::run_gather(*num->S, shift, num->L, out, (hipStream_t)stream);
+  if (e != 0) return hip_fail(e);
+  return PXS_OK;
+}
+
+pxs_status pxs_get_diag(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream) {
+  if (!num || !out || shift < 0 || shift >= num->nshift) return PXS_EINVAL;
+  if (num->selinv_done) return PXS_ESTATE;
+  int e = pxs::run_get_diag(*num->S, shift, true, num->L, out, (hipStream_t)stream);
+  if (e != 0) return hip_fail(e);
+  return PXS_OK;
+}
+
+pxs_status pxs_inertia(pxs_symbolic sym, const double* Hval, const double* Sval, int32_t nshift,
+                       const double* eps, void* Lbuf, void* work, int64_t* neg_count, int64_t* info,
+                       void* stream) {
+  pxs_status s0 = check_numeric_args(sym, Hval, Sval, nshift, Lbuf, work);
+  if (s0 != PXS_OK) return s0;
+  if (!eps || !neg_count) return PXS_EINVAL;
+  std::vector<double> sh(2 * nshift, 0.0);
+  for (int32_t q = 0; q < nshift; ++q) {
+    if (!std::isfinite(eps[q])) return PXS_EINVAL;
+    sh[2 * q] = eps[q];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int e = pxs::run_factor<false>(sym->S, Hval, Sval, nshift, sh.data(), Lbuf, work, st);
+  if (e != 0) return hip_fail(e);
+  std::vector<int64_t> tmp(2 * pxs::MAX_SHIFTS);
+  hipError_t he = hipMemcpyAsync(tmp.data(), (char*)work + pxs::WK_INFO, sizeof(int64_t) * 2 * pxs::MAX_SHIFTS,
+                                 hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(he);
+  bool tiny = false;
+  for (int32_t q = 0; q < nshift; ++q) {
+    neg_count[q] = tmp[pxs::MAX_SHIFTS + q];
+    if (info) info[q] = tmp[q];
+    tiny = tiny || tmp[q] != 0;
+  }
+  return tiny ? PXS_TINY_PIVOT : PXS_OK;
+}
+
+pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double* Sval, double beta,
+                              double dE, double mu, int32_t P, int32_t nsets, void* Lbuf, void* work,
+                              double* out, double* traces, int64_t* info, pxs_c64* shifts,
+                              pxs_c64* weights, void* stream) {
+  if (nsets < 1 || nsets > 4 || P < 2 || (P & 1) || P > pxs::MAX_SHIFTS) return PXS_EINVAL;
+  std::vector<pxs_c64> sh(P), wt((size_t)nsets * P);
+  pxs_status s = pxs_poles(beta, dE, mu, P, nsets, sh.data(), wt.data());
+  if (s != PXS_OK) return s;
+  pxs_numeric num = nullptr;
+  s = pxs_factor(sym, Hval, Sval, P, sh.data(), Lbuf, work, info, stream, &num);
+  if (s < 0) return s;
+  pxs_status piv = s;
+  s = pxs_selinv(num, stream);
+  if (s == PXS_OK) s = pxs_pole_sum(num, nsets, wt.data(), out, traces, stream);
+  pxs_free_numeric(num);
+  if (s != PXS_OK) return s;
+  if (shifts) std::memcpy(shifts, sh.data(), sizeof(pxs_c64) * P);
+  if (weights) std::memcpy(weights, wt.data(), sizeof(pxs_c64) * nsets * P);
+  return piv;
+}
+
+void pxs_free_symbolic(pxs_symbolic sym) { delete sym; }
+void pxs_free_numeric(pxs_numeric num) { delete num; }
+
+}  // extern "C"

@@ -1,0 +1,35 @@
+// Launch entry points of the numeric phases (numeric.hip) and the layout of
+// the fixed part of the workspace.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pxs_internal.h"
+
+namespace pxs {
+
+constexpr int MAX_SHIFTS = 4096;
+constexpr int ABSMAX_BLOCKS = 512;
+constexpr int POLESUM_BLOCKS = 1024;
+
+// byte offsets inside the fixed workspace region (work_fixed = 1 MiB)
+constexpr int64_t WK_ABSMAX = 0;             // 2 doubles: max|H|, max|S|
+constexpr int64_t WK_ABSMAX_PART = 256;      // ABSMAX_BLOCKS x 2 doubles
+constexpr int64_t WK_POLESUM_PART = 16384;   // POLESUM_BLOCKS x 8 doubles
+constexpr int64_t WK_TRACES = 90112;         // 8 doubles
+constexpr int64_t WK_SHIFTS = 131072;        // MAX_SHIFTS complex
+constexpr int64_t WK_INFO = 196608;          // MAX_SHIFTS int64
+constexpr int64_t WK_NEGC = WK_INFO + 8 * MAX_SHIFTS;   // MAX_SHIFTS int64
+constexpr int64_t WK_WEIGHTS = 262144;       // 4 x MAX_SHIFTS complex
+constexpr int64_t WK_FIXED_BYTES = 1 << 20;
+
+template <bool CPLX>
+int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
+               const double* shifts_host, void* L, void* work, hipStream_t st);
+int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st);
+int run_pole_sum(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
+                 const double* Sv, int nsets, const double* weights_host, double* out,
+                 hipStream_t st);
+int run_gather(const Symbolic& S, int shift, const void* L, void* out, hipStream_t st);
+int run_get_diag(const Symbolic& S, int shift, bool cplx, const void* L, void* out, hipStream_t st);
+
+}  // namespace pxs

@@ -1,0 +1,842 @@
+// Numeric phases on gfx950 (MI355X): assembly of the shifted matrices, the
+// supernodal LDL^T factorization, selected inversion, pole sums and inertia.
+//
+// Paper, Sec. II.A-II.B: for A = H - z S (complex symmetric) compute
+// A = L D L^T (L unit lower, D diagonal) and then the entries of A^{-1} on
+// the pattern of L; the factorization traverses the elimination tree from the
+// leaves to the root and selected inversion from the root to the leaves, both
+// as dense matrix products on supernodes.  Sec. II.C: for real shifts the
+// number of negative d_k is the inertia count.
+//
+// Execution model: every launch covers all shifts of a batch (grid.y) and all
+// tiles of one panel (a <= 64-column slice of a supernode).  Panels run in
+// factor order (left to right, supernodes in postorder) and SelInv order (the
+// reverse); within a launch, workgroups own disjoint outputs, so there are no
+// atomics on matrix data and results do not depend on scheduling.
+//
+// Per panel p of supernode J (row list E_J, own columns first), with
+// B = rows of E_J below the panel's diagonal block:
+//   factor:  k_diag   dense LDL^T of the wp x wp diagonal block in LDS; stores
+//                     D on the diagonal and L_pp^{-1} below it
+//            k_trsm   L_Bp = A_Bp L_pp^{-T} D_p^{-1}
+//            k_update A_BB -= L_Bp D_p L_Bp^T, scattered through the maps into
+//                     the later columns of J and into ancestor supernodes
+//   selinv:  k_lhat   W = L_Bp L_pp^{-1}                       (workspace)
+//            k_selinv_off   Z_Bp = -Z_BB W   (Z_BB gathered, symmetric)
+//            k_selinv_diag_* Z_pp = L_pp^{-T} D_p^{-1} L_pp^{-1} - W^T Z_Bp
+// The products run on FP64 MFMA (v_mfma_f64_16x16x4f64): a complex product
+// is four real MFMAs on split real/imaginary LDS tiles.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "pxs_internal.h"
+#include "numeric.h"
+
+namespace pxs {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+constexpr int NT = 256;   // threads per workgroup (4 wave64)
+constexpr int TM = 64;    // tile rows (m) and columns (n)
+constexpr int KC = 16;    // k-chunk staged in LDS
+constexpr int LDP = 65;   // padded LDS row (doubles)
+
+struct cplx {
+  double re, im;
+};
+
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ cplx cinv(cplx a) {
+  double d = a.re * a.re + a.im * a.im;
+  return {a.re / d, -a.im / d};
+}
+
+template <bool CPLX>
+__device__ __forceinline__ cplx ld_elem(const double* base, int64_t e) {
+  if (CPLX) {
+    const double2 v = *reinterpret_cast<const double2*>(base + 2 * e);
+    return {v.x, v.y};
+  }
+  return {base[e], 0.0};
+}
+template <bool CPLX>
+__device__ __forceinline__ void st_elem(double* base, int64_t e, cplx v) {
+  if (CPLX) {
+    *reinterpret_cast<double2*>(base + 2 * e) = make_double2(v.re, v.im);
+  } else {
+    base[e] = v.re;
+  }
+}
+
+// --------------------------------------------------------------------------
+// MFMA tile engine: a 256-thread workgroup accumulates a 64 x 64 tile
+// P[m][n] = sum_k A[m][k] B[k][n].  Wave w owns rows 32*(w>>1) .. +32 and
+// columns 32*(w&1) .. +32 as 2 x 2 blocks of 16 x 16.  Operands are staged
+// in LDS as As[k][m], Bs[k][n] (real and imaginary parts split).
+// v_mfma_f64_16x16x4f64 lane layout (lane l, 0..63):
+//   A operand: A[l % 16][l / 16];  B operand: B[l / 16][l % 16];
+//   result register r: D[l / 16 + 4 r][l % 16].
+// --------------------------------------------------------------------------
+template <bool CPLX>
+struct Acc {
+  dbl4 re[2][2];
+  dbl4 im[2][2];
+  __device__ void zero() {
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        re[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+        if (CPLX) im[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+      }
+  }
+};
+
+template <bool CPLX>
+struct Stage {
+  double a_re[KC][LDP];
+  double a_im[CPLX ? KC : 1][LDP];
+  double b_re[KC][LDP];
+  double b_im[CPLX ? KC : 1][LDP];
+};
+
+template <bool CPLX>
+__device__ __forceinline__ void mfma_chunk(Acc<CPLX>& acc, const Stage<CPLX>& s) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < KC / 4; ++ks) {
+    const int k = ks * 4 + lk;
+    double ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      ar[t] = s.a_re[k][wm + t * 16 + li];
+      br[t] = s.b_re[k][wn + t * 16 + li];
+      if (CPLX) {
+        ai[t] = s.a_im[k][wm + t * 16 + li];
+        bi[t] = s.b_im[k][wn + t * 16 + li];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc.re[a][b], 0, 0, 0);
+        if (CPLX) {
+          acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], bi[b], acc.re[a][b], 0, 0, 0);
+          acc.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], bi[b], acc.im[a][b], 0, 0, 0);
+          acc.im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], acc.im[a][b], 0, 0, 0);
+        }
+      }
+  }
+}
+
+// Visits every accumulator element as (m, n, value).
+template <bool CPLX, class F>
+__device__ __forceinline__ void acc_foreach(const Acc<CPLX>& acc, F f) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = wm + a * 16 + (lane >> 4) + 4 * r;
+        const int n = wn + b * 16 + (lane & 15);
+        cplx v{acc.re[a][b][r], CPLX ? acc.im[a][b][r] : 0.0};
+        f(m, n, v);
+      }
+}
+
+// Staging: fill (m or n, k) of one chunk from a functor get(idx, k) -> cplx.
+// FAST_K = false: consecutive threads take consecutive idx (memory contiguous
+// along idx); FAST_K = true: consecutive threads take consecutive k.
+template <bool CPLX, bool FAST_K, class G>
+__device__ __forceinline__ void stage_op(double (*re)[LDP], double (*im)[LDP], G get) {
+  const int t = threadIdx.x;
+  cplx v[4];
+  int ii[4], kk[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (!FAST_K) {
+      ii[j] = t & 63;
+      kk[j] = (t >> 6) + 4 * j;
+    } else {
+      kk[j] = t & 15;
+      ii[j] = (t >> 4) + 16 * j;
+    }
+    v[j] = get(ii[j], kk[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    re[kk[j]][ii[j]] = v[j].re;
+    if (CPLX) im[kk[j]][ii[j]] = v[j].im;
+  }
+}
+
+// --------------------------------------------------------------------------
+// small kernels
+// --------------------------------------------------------------------------
+__global__ void k_fill_zero(double2* p, int64_t n2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n2; i += stride) p[i] = make_double2(0.0, 0.0);
+}
+
+__global__ void k_zero_i64(int64_t* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// max |H| and max |S| (two-stage, deterministic)
+__global__ void k_absmax_partial(const double* __restrict__ H, const double* __restrict__ S,
+                                 int64_t nnz, double* partial) {
+  __shared__ double sh[2][NT];
+  double mh = 0.0, ms = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * NT) {
+    mh = fmax(mh, fabs(H[i]));
+    ms = fmax(ms, fabs(S[i]));
+  }
+  sh[0][threadIdx.x] = mh;
+  sh[1][threadIdx.x] = ms;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + s]);
+      sh[1][threadIdx.x] = fmax(sh[1][threadIdx.x], sh[1][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sh[0][0];
+    partial[2 * blockIdx.x + 1] = sh[1][0];
+  }
+}
+__global__ void k_absmax_final(const double* partial, int nb, double* out) {
+  if (threadIdx.x == 0) {
+    double mh = 0.0, ms = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      mh = fmax(mh, partial[2 * b]);
+      ms = fmax(ms, partial[2 * b + 1]);
+    }
+    out[0] = mh;
+    out[1] = ms;
+  }
+}
+
+// A_l = H - w_l S on the input pattern (the rest of the storage is zero).
+template <bool CPLX>
+__global__ void k_assemble(double* __restrict__ L, int64_t stride, const double* __restrict__ H,
+                           const double* __restrict__ S, const int64_t* __restrict__ eoff,
+                           int64_t nnz, const double* __restrict__ shifts) {
+  const int sh = blockIdx.y;
+  const double wr = shifts[2 * sh], wi = shifts[2 * sh + 1];
+  double* Ls = L + (CPLX ? 2 : 1) * stride * sh;
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * NT) {
+    const double h = H[k], s = S[k];
+    st_elem<CPLX>(Ls, eoff[k], cplx{h - wr * s, -wi * s});
+  }
+}
+
+// --------------------------------------------------------------------------
+// factor kernels
+// --------------------------------------------------------------------------
+struct PanelK {
+  int64_t off;     // storage offset of the supernode
+  int64_t cm;      // index of the supernode's row list in colmap/colseg
+  int32_t ld;      // leading dimension of the supernode
+  int32_t p0;      // panel's first column (position in the row list)
+  int32_t wp;      // panel width
+  int32_t nb;      // rows below the panel's diagonal block
+  int32_t col0;    // new index of the panel's first column
+  int32_t split;   // split-K pieces (SelInv diagonal update)
+};
+
+struct Common {
+  double* L;               // factor storage of shift 0
+  int64_t stride;          // elements per shift
+  const int64_t* colmap;
+  const int64_t* colseg;
+  const int32_t* relpos;
+  double* work;            // workspace base
+  int64_t wps;             // workspace bytes per shift
+  int64_t wfix;            // fixed workspace bytes
+  const double* shifts;    // device, 2 doubles per shift
+  const double* absmax;    // device, max|H|, max|S|
+  int64_t* info;           // device, per shift
+  int64_t* negc;           // device, per shift
+  double pivtol;
+};
+
+template <bool CPLX>
+__device__ __forceinline__ double* shift_base(const Common& c, int sh) {
+  return c.L + (CPLX ? 2 : 1) * c.stride * sh;
+}
+
+// Dense LDL^T of the panel's wp x wp diagonal block, then L_pp^{-1} in place.
+template <bool CPLX>
+__global__ void __launch_bounds__(NT) k_diag(Common c, PanelK p) {
+  __shared__ double a_re[64][LDP];   // a[col][row]
+  __shared__ double a_im[CPLX ? 64 : 1][LDP];
+  const int sh = blockIdx.y;
+  double* Ls = shift_base<CPLX>(c, sh);
+  const int wp = p.wp;
+  const int t = threadIdx.x;
+  const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;
+  for (int idx = t; idx < wp * wp; idx += NT) {
+    const int cc = idx / wp, r = idx % wp;
+    cplx v{0.0, 0.0};
+    if (r >= cc) v = ld_elem<CPLX>(Ls, dbase + (int64_t)cc * p.ld + r);
+    a_re[cc][r] = v.re;
+    if (CPLX) a_im[cc][r] = v.im;
+  }
+  __syncthreads();
+  const double wabs = sqrt(c.shifts[2 * sh] * c.shifts[2 * sh] + c.shifts[2 * sh + 1] * c.shifts[2 * sh + 1]);
+  const double thr = c.pivtol * (c.absmax[0] + (CPLX ? wabs : fabs(c.shifts[2 * sh])) * c.absmax[1]);
+  int bad = 0;
+  int neg = 0;
+  const int r = t & 63, cg = t >> 6;
+  for (int k = 0; k < wp; ++k) {
+    const cplx d{a_re[k][k], CPLX ? a_im[k][k] : 0.0};
+    if (t == 0) {
+      const double ad = CPLX ? sqrt(d.re * d.re + d.im * d.im) : fabs(d.re);
+      if (!(ad >= thr) && bad == 0) bad = p.col0 + k + 1;
+      if (!CPLX && d.re < 0.0) ++neg;
+    }
+    const cplx id = CPLX ? cinv(d) : cplx{1.0 / d.re, 0.0};
+    if (r > k && r < wp) {
+      const cplx lrk{a_re[k][r], CPLX ? a_im[k][r] : 0.0};
+      for (int cc = k + 1 + cg; cc <= r; cc += 4) {
+        const cplx lck{a_re[k][cc], CPLX ? a_im[k][cc] : 0.0};
+        const cplx f = cmul(lrk, cmul(lck, id));
+        a_re[cc][r] -= f.re;
+        if (CPLX) a_im[cc][r] -= f.im;
+      }
+    }
+    __syncthreads();
+    if (t > k && t < wp) {
+      const cplx v{a_re[k][t], CPLX ? a_im[k][t] : 0.0};
+      const cplx s = cmul(v, id);
+      a_re[k][t] = s.re;
+      if (CPLX) a_im[k][t] = s.im;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    // panels run in column order, so the first flagged column wins
+    if (bad) atomicCAS((unsigned long long*)&c.info[sh], 0ull, (unsigned long long)bad);
+    if (!CPLX && neg) atomicAdd((unsigned long long*)&c.negc[sh], (unsigned long long)neg);
+  }
+  // in-place inverse of the unit lower factor: column j of L^{-1} is
+  // x_i = -sum_{k=j+1..i} Linv[i][k] L[k][j] (Linv[i][i] = 1), using columns
+  // > j that are already inverted and the original column j.
+  for (int j = wp - 2; j >= 0; --j) {
+    cplx x{0.0, 0.0};
+    if (t > j && t < wp) {
+      cplx s{a_re[j][t], CPLX ? a_im[j][t] : 0.0};
+      for (int k = j + 1; k < t; ++k) {
+        const cplx li{a_re[k][t], CPLX ? a_im[k][t] : 0.0};
+        const cplx lk{a_re[j][k], CPLX ? a_im[j][k] : 0.0};
+        const cplx pr = cmul(li, lk);
+        s.re += pr.re;
+        s.im += pr.im;
+      }
+      x = {-s.re, -s.im};
+    }
+    __syncthreads();
+    if (t > j && t < wp) {
+      a_re[j][t] = x.re;
+      if (CPLX) a_im[j][t] = x.im;
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < wp * wp; idx += NT) {
+    const int cc = idx / wp, rr = idx % wp;
+    if (rr >= cc) st_elem<CPLX>(Ls, dbase + (int64_t)cc * p.ld + rr, cplx{a_re[cc][rr], CPLX ? a_im[cc][rr] : 0.0});
+  }
+}
+
+// L_Bp = A_Bp L_pp^{-T} D^{-1}: P[c][i] = sum_k Linv[c][k] A[i][k], then / d_c.
+template <bool CPLX>
+__global__ void __launch_bounds__(NT) k_trsm(Common c, PanelK p) {
+  __shared__ Stage<CPLX> s;
+  __shared__ cplx dinv[64];
+  const int sh = blockIdx.y;
+  double* Ls = shift_base<CPLX>(c, sh);
+  const int i0 = blockIdx.x * TM;
+  const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;   // (p0, p0)
+  const int64_t rbase = dbase + p.wp;                          // first row below
+  if (threadIdx.x < p.wp) {
+    const cplx d = ld_elem<CPLX>(Ls, dbase + (int64_t)threadIdx.x * p.ld + threadIdx.x);
+    dinv[threadIdx.x] = CPLX ? cinv(d) : cplx{1.0 / d.re, 0.0};
+  }
+  Acc<CPLX> acc;
+  acc.zero();
+  for (int k0 = 0; k0 < p.wp; k0 += KC) {
+    __syncthreads();
+    // A operand: Linv[c][k] (column k of the diagonal block, rows c)
+    stage_op<CPLX, false>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
+      const int kg = k0 + k;
+      if (m >= p.wp || kg >= p.wp || m < kg) return cplx{0.0, 0.0};
+      if (m == kg) return cplx{1.0, 0.0};
+      return ld_elem<CPLX>(Ls, dbase + (int64_t)kg * p.ld + m);
+    });
+    // B operand: A[i][k]
+    stage_op<CPLX, false>(s.b_re, s.b_im, [&](int n, int k) -> cplx {
+      const int kg = k0 + k, ig = i0 + n;
+      if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
+      return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
+    });
+    __syncthreads();
+    mfma_chunk<CPLX>(acc, s);
+  }
+  acc_foreach<CPLX>(acc, [&](int m, int n, cplx v) {
+    const int ig = i0 + n;
+    if (m < p.wp && ig < p.nb) st_elem<CPLX>(Ls, rbase + (int64_t)m * p.ld + ig, cmul(v, dinv[m]));
+  });
+}
+
+__device__ __forceinline__ void tri_index(int b, int& ti, int& tj) {
+  // b enumerates the pairs (ti >= tj) row by row: b = ti (ti + 1) / 2 + tj
+  int x = (int)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while ((x + 1) * (x + 2) / 2 <= b) ++x;
+  while (x * (x + 1) / 2 > b) --x;
+  ti = x;
+  tj = b - x * (x + 1) / 2;
+}
+
+// A_BB -= L_Bp D L_Bp^T on lower tiles (ti >= tj), scattered through the maps.
+// P[j][i] = sum_k (d_k L[j][k]) L[i][k].
+template <bool CPLX>
+__global__ void __launch_bounds__(NT) k_update(Common c, PanelK p) {
+  __shared__ Stage<CPLX> s;
+  __shared__ cplx dk[64];
+  const int sh = blockIdx.y;
+  double* Ls = shift_base<CPLX>(c, sh);
+  int ti, tj;
+  tri_index(blockIdx.x, ti, tj);
+  const int i0 = ti * TM, j0 = tj * TM;
+  const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;
+  const int64_t rbase = dbase + p.wp;
+  if (threadIdx.x < p.wp) dk[threadIdx.x] = ld_elem<CPLX>(Ls, dbase + (int64_t)threadIdx.x * p.ld + threadIdx.x);
+  Acc<CPLX> acc;
+  acc.zero();
+  for (int k0 = 0; k0 < p.wp; k0 += KC) {
+    __syncthreads();
+    stage_op<CPLX, false>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
+      const int kg = k0 + k, jg = j0 + m;
+      if (kg >= p.wp || jg >= p.nb) return cplx{0.0, 0.0};
+      return cmul(dk[kg], ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + jg));
+    });
+    stage_op<CPLX, false>(s.b_re, s.b_im, [&](int n, int k) -> cplx {
+      const int kg = k0 + k, ig = i0 + n;
+      if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
+      return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
+    });
+    __syncthreads();
+    mfma_chunk<CPLX>(acc, s);
+  }
+  const int base = p.p0 + p.wp;   // row-list position of the first row below
+  const int64_t* cmap = c.colmap + p.cm;
+  const int64_t* cseg = c.colseg + p.cm;
+  acc_foreach<CPLX>(acc, [&](int m, int n, cplx v) {
+    const int jg = j0 + m, ig = i0 + n;
+    if (jg < p.nb && ig < p.nb && ig >= jg) {
+      const int qj = base + jg, qi = base + ig;
+      const int64_t e = cmap[qj] + c.relpos[cseg[qj] + qi];
+      cplx o = ld_elem<CPLX>(Ls, e);
+      o.re -= v.re;
+      o.im -= v.im;
+      st_elem<CPLX>(Ls, e, o);
+    }
+  });
+}
+
+// --------------------------------------------------------------------------
+// selected inversion kernels (complex only)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double* wbase(const Common& c, int sh) {
+  return (double*)((char*)c.work + c.wfix + c.wps * sh);
+}
+
+// W = L_Bp Linv: P[c][i] = sum_k Linv[k][c] L[i][k]; W stored W[c * nb + i].
+__global__ void __launch_bounds__(NT) k_lhat(Common c, PanelK p) {
+  __shared__ Stage<true> s;
+  const int sh = blockIdx.y;
+  double* Ls = shift_base<true>(c, sh);
+  double* W = wbase(c, sh);
+  const int i0 = blockIdx.x * TM;
+  const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;
+  const int64_t rbase = dbase + p.wp;
+  Acc<true> acc;
+  acc.zero();
+  for (int k0 = 0; k0 < p.wp; k0 += KC) {
+    __syncthreads();
+    // A[c][k] = Linv[k][c]: column c of the diagonal block, rows k (fast k)
+    stage_op<true, true>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
+      const int kg = k0 + k;
+      if (m >= p.wp || kg >= p.wp || kg < m) return cplx{0.0, 0.0};
+      if (kg == m) return cplx{1.0, 0.0};
+      return ld_elem<true>(Ls, dbase + (int64_t)m * p.ld + kg);
+    });
+    stage_op<true, false>(s.b_re, s.b_im, [&](int n, int k) -> cplx {
+      const int kg = k0 + k, ig = i0 + n;
+      if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
+      return ld_elem<true>(Ls, rbase + (int64_t)kg * p.ld + ig);
+    });
+    __syncthreads();
+    mfma_chunk<true>(acc, s);
+  }
+  acc_foreach<true>(acc, [&](int m, int n, cplx v) {
+    const int ig = i0 + n;
+    if (m < p.wp && ig < p.nb) st_elem<true>(W, (int64_t)m * p.nb + ig, v);
+  });
+}
+
+// Z_Bp = -Z_BB W: P[c][i] = sum_k W[k][c] Z(k, i), Z_BB gathered (symmetric).
+__global__ void __launch_bounds__(NT) k_selinv_off(Common c, PanelK p) {
+  __shared__ Stage<true> s;
+  const int sh = blockIdx.y;
+  double* Ls = shift_base<true>(c, sh);
+  const double* W = wbase(c, sh);
+  const int i0 = blockIdx.x * TM;
+  const int base = p.p0 + p.wp;
+  const int64_t* cmap = c.colmap + p.cm;
+  const int64_t* cseg = c.colseg + p.cm;
+  const int32_t* rel = c.relpos;
+  Acc<true> acc;
+  acc.zero();
+  for (int k0 = 0; k0 < p.nb; k0 += KC) {
+    __syncthreads();
+    stage_op<true, true>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
+      const int kg = k0 + k;
+      if (m >= p.wp || kg >= p.nb) return cplx{0.0, 0.0};
+      return ld_elem<true>(W, (int64_t)m * p.nb + kg);
+    });
+    auto getz = [&](int n, int k) -> cplx {
+      const int kg = k0 + k, ig = i0 + n;
+      if (kg >= p.nb || ig >= p.nb) return cplx{0.0, 0.0};
+      const int qk = base + kg, qi = base + ig;
+      const int64_t e = (qi >= qk) ? cmap[qk] + rel[cseg[qk] + qi] : cmap[qi] + rel[cseg[qi] + qk];
+      return ld_elem<true>(Ls, e);
+    };
+    if (k0 + KC <= i0 + 1) {
+      stage_op<true, false>(s.b_re, s.b_im, getz);   // all below the diagonal: rows contiguous
+    } else {
+      stage_op<true, true>(s.b_re, s.b_im, getz);    // above (or across) the diagonal
+    }
+    __syncthreads();
+    mfma_chunk<true>(acc, s);
+  }
+  const int64_t rbase = p.off + (int64_t)p.p0 * p.ld + base;
+  acc_foreach<true>(acc, [&](int m, int n, cplx v) {
+    const int ig = i0 + n;
+    if (m < p.wp && ig < p.nb) st_elem<true>(Ls, rbase + (int64_t)m * p.ld + ig, cplx{-v.re, -v.im});
+  });
+}
+
+// Partial W^T Z_Bp over k in [split * 512, ...): P[c][r] = sum_k Z[k][c] W[k][r].
+__global__ void __launch_bounds__(NT) k_selinv_diag_partial(Common c, PanelK p) {
+  __shared__ Stage<true> s;
+  const int sh = blockIdx.y;
+  const int sp = blockIdx.x;
+  double* Ls = shift_base<true>(c, sh);
+  double* W = wbase(c, sh);
+  double* part = W + 2 * (int64_t)p.nb * p.wp;   // after W: split x 64 x 64 complex
+  const int base = p.p0 + p.wp;
+  const int64_t rbase = p.off + (int64_t)p.p0 * p.ld + base;
+  const int kb = sp * 512, ke = min(p.nb, kb + 512);
+  Acc<true> acc;
+  acc.zero();
+  for (int k0 = kb; k0 < ke; k0 += KC) {
+    __syncthreads();
+    stage_op<true, true>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
+      const int kg = k0 + k;
+      if (m >= p.wp || kg >= ke) return cplx{0.0, 0.0};
+      return ld_elem<true>(Ls, rbase + (int64_t)m * p.ld + kg);
+    });
+    stage_op<true, true>(s.b_re, s.b_im, [&](int n, int k) -> cplx {
+      const int kg = k0 + k;
+      if (n >= p.wp || kg >= ke) return cplx{0.0, 0.0};
+      return ld_elem<true>(W, (int64_t)n * p.nb + kg);
+    });
+    __syncthreads();
+    mfma_chunk<true>(acc, s);
+  }
+  double* out = part + 2 * (int64_t)sp * 64 * 64;
+  acc_foreach<true>(acc, [&](int m, int n, cplx v) { st_elem<true>(out, (int64_t)m * 64 + n, v); });
+}
+
+// Z_pp = Linv^T D^{-1} Linv - sum of the partials, written over the diagonal block.
+__global__ void __launch_bounds__(NT) k_selinv_diag_final(Common c, PanelK p) {
+  __shared__ double l_re[64][LDP];   // l[col][row] = Linv[row][col]
+  __shared__ double l_im[64][LDP];
+  __shared__ cplx dinv[64];
+  const int sh = blockIdx.y;
+  double* Ls = shift_base<true>(c, sh);
+  const double* W = wbase(c, sh);
+  const double* part = W + 2 * (int64_t)p.nb * p.wp;
+  const int wp = p.wp;
+  const int t = threadIdx.x;
+  const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;
+  for (int idx = t; idx < wp * wp; idx += NT) {
+    const int cc = idx / wp, r = idx % wp;
+    cplx v{0.0, 0.0};
+    if (r > cc) v = ld_elem<true>(Ls, dbase + (int64_t)cc * p.ld + r);
+    if (r == cc) {
+      v = cplx{1.0, 0.0};
+      dinv[r] = cinv(ld_elem<true>(Ls, dbase + (int64_t)cc * p.ld + r));
+    }
+    l_re[cc][r] = v.re;
+    l_im[cc][r] = v.im;
+  }
+  __syncthreads();
+  const int nsplit = (p.nb > 0) ? p.split : 0;
+  for (int idx = t; idx < wp * wp; idx += NT) {
+    const int cc = idx / wp, r = idx % wp;   // element (r, cc)
+    // sum_{k >= max(r, cc)} Linv[k][r] dinv[k] Linv[k][cc]
+    cplx s{0.0, 0.0};
+    for (int k = max(r, cc); k < wp; ++k) {
+      const cplx a{l_re[r][k], l_im[r][k]};
+      const cplx b{l_re[cc][k], l_im[cc][k]};
+      const cplx q = cmul(cmul(a, dinv[k]), b);
+      s.re += q.re;
+      s.im += q.im;
+    }
+    // partial[m = cc][n = r] holds (W^T Z_Bp)[r][cc]
+    for (int sp = 0; sp < nsplit; ++sp) {
+      const cplx q = ld_elem<true>(part + 2 * (int64_t)sp * 64 * 64, (int64_t)cc * 64 + r);
+      s.re -= q.re;
+      s.im -= q.im;
+    }
+    // each (r, cc) is computed by exactly one thread, and the diagonal block
+    // in global memory is no longer read (Linv and D sit in LDS)
+    st_elem<true>(Ls, dbase + (int64_t)cc * p.ld + r, s);
+  }
+}
+
+// --------------------------------------------------------------------------
+// pole sums, extraction
+// --------------------------------------------------------------------------
+// out[g][k] = sum_l Im(omega_{g,l} Z_l[k]); per-block partial traces.
+__global__ void __launch_bounds__(NT) k_pole_sum(const double* __restrict__ L, int64_t stride,
+                                                 int nshift, const double* __restrict__ wts,
+                                                 int nsets, const int64_t* __restrict__ eoff,
+                                                 const int32_t* __restrict__ ediag, int64_t nnz,
+                                                 const double* __restrict__ H,
+                                                 const double* __restrict__ S, double* out,
+                                                 double* partial) {
+  __shared__ double red[8][NT];
+  double tr[8];
+  for (int q = 0; q < 8; ++q) tr[q] = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * NT) {
+    const int64_t e = eoff[k];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int l = 0; l < nshift; ++l) {
+      const double2 z = *reinterpret_cast<const double2*>(L + 2 * (stride * l + e));
+      for (int g = 0; g < nsets; ++g) {
+        const double wr = wts[2 * (g * nshift + l)], wi = wts[2 * (g * nshift + l) + 1];
+        acc[g] += wr * z.y + wi * z.x;
+      }
+    }
+    const double mult = ediag[k] ? 1.0 : 2.0;
+    for (int g = 0; g < nsets; ++g) {
+      out[(int64_t)g * nnz + k] = acc[g];
+      tr[2 * g] += mult * acc[g] * S[k];
+      tr[2 * g + 1] += mult * acc[g] * H[k];
+    }
+  }
+  for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = tr[q];
+  __syncthreads();
+  for (int s2 = NT / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2)
+      for (int q = 0; q < 8; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) partial[8 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_sum_partials(const double* partial, int nb, double* out) {
+  const int q = threadIdx.x;
+  if (q < 8) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[8 * b + q];
+    out[q] = s;
+  }
+}
+
+__global__ void k_gather(const double* __restrict__ L, const int64_t* __restrict__ eoff,
+                         int64_t nnz, double2* out) {
+  for (int64_t k = (int64_t)blockIdx.x * NT + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * NT)
+    out[k] = *reinterpret_cast<const double2*>(L + 2 * eoff[k]);
+}
+
+__global__ void k_get_diag(const double* __restrict__ L, const int64_t* __restrict__ diagoff, int n,
+                           int cplx_elems, double2* out) {
+  // diagoff[j] = element offset of the diagonal entry of new column j
+  const int j = blockIdx.x * NT + threadIdx.x;
+  if (j < n) {
+    const int64_t e = diagoff[j];
+    out[j] = cplx_elems ? *reinterpret_cast<const double2*>(L + 2 * e) : make_double2(L[e], 0.0);
+  }
+}
+
+// --------------------------------------------------------------------------
+// host orchestration
+// --------------------------------------------------------------------------
+namespace {
+
+inline int blocks_for(int64_t n, int cap) {
+  int64_t b = (n + NT - 1) / NT;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+PanelK panel_args(const Symbolic& S, const Panel& P) {
+  PanelK k;
+  k.off = S.off[P.J];
+  k.cm = S.rowptr[P.J];
+  k.ld = S.ld[P.J];
+  k.p0 = P.p0;
+  k.wp = P.wp;
+  k.nb = P.nb_rows;
+  k.col0 = S.sfirst[P.J] + P.p0;
+  k.split = split_count(P.nb_rows);
+  return k;
+}
+
+}  // namespace
+
+Common make_common(const Symbolic& S, void* L, void* work) {
+  Common c;
+  c.L = (double*)L;
+  c.stride = S.nnzL_store;
+  const char* m = (const char*)S.dmaps;
+  c.colmap = (const int64_t*)(m + S.o_colmap);
+  c.colseg = (const int64_t*)(m + S.o_colseg);
+  c.relpos = (const int32_t*)(m + S.o_relpos);
+  c.work = (double*)work;
+  c.wps = S.work_per_shift;
+  c.wfix = S.work_fixed;
+  char* w = (char*)work;
+  c.absmax = (const double*)(w + WK_ABSMAX);
+  c.shifts = (const double*)(w + WK_SHIFTS);
+  c.info = (int64_t*)(w + WK_INFO);
+  c.negc = (int64_t*)(w + WK_NEGC);
+  c.pivtol = S.pivot_tol;
+  return c;
+}
+
+#define PXS_CHECK_LAUNCH()                         \
+  do {                                             \
+    hipError_t e_ = hipGetLastError();             \
+    if (e_ != hipSuccess) return (int)e_;          \
+  } while (0)
+
+template <bool CPLX>
+int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
+               const double* shifts_host, void* L, void* work, hipStream_t st) {
+  char* w = (char*)work;
+  hipError_t e = hipMemcpyAsync(w + WK_SHIFTS, shifts_host, sizeof(double) * 2 * nshift,
+                                hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(k_zero_i64, dim3((2 * MAX_SHIFTS + NT - 1) / NT), dim3(NT), 0, st,
+                     (int64_t*)(w + WK_INFO), 2 * MAX_SHIFTS);
+  PXS_CHECK_LAUNCH();
+  const char* m = (const char*)S.dmaps;
+  const int64_t* eoff = (const int64_t*)(m + S.o_entry_off);
+  const int nbm = blocks_for(S.nnz_lower, ABSMAX_BLOCKS);
+  hipLaunchKernelGGL(k_absmax_partial, dim3(nbm), dim3(NT), 0, st, H, Sv, S.nnz_lower,
+                     (double*)(w + WK_ABSMAX_PART));
+  hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(64), 0, st, (const double*)(w + WK_ABSMAX_PART),
+                     nbm, (double*)(w + WK_ABSMAX));
+  PXS_CHECK_LAUNCH();
+  const int64_t total_d = (CPLX ? 2 : 1) * S.nnzL_store * (int64_t)nshift;   // doubles
+  hipLaunchKernelGGL(k_fill_zero, dim3(blocks_for(total_d / 2 + 1, 8192)), dim3(NT), 0, st,
+                     (double2*)L, total_d / 2);
+  if (total_d & 1)
+    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, st, (double2*)((double*)L + total_d - 2), (int64_t)1);
+  PXS_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_assemble<CPLX>, dim3(blocks_for(S.nnz_lower, 2048), nshift), dim3(NT), 0, st,
+                     (double*)L, S.nnzL_store, H, Sv, eoff, S.nnz_lower, (const double*)(w + WK_SHIFTS));
+  PXS_CHECK_LAUNCH();
+  Common c = make_common(S, L, work);
+  for (const Panel& P : S.panels) {
+    PanelK k = panel_args(S, P);
+    hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NT), 0, st, c, k);
+    if (k.nb > 0) {
+      const int nt = (k.nb + TM - 1) / TM;
+      hipLaunchKernelGGL(k_trsm<CPLX>, dim3(nt, nshift), dim3(NT), 0, st, c, k);
+      hipLaunchKernelGGL(k_update<CPLX>, dim3(nt * (nt + 1) / 2, nshift), dim3(NT), 0, st, c, k);
+    }
+    PXS_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+template int run_factor<true>(const Symbolic&, const double*, const double*, int, const double*, void*, void*, hipStream_t);
+template int run_factor<false>(const Symbolic&, const double*, const double*, int, const double*, void*, void*, hipStream_t);
+
+int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st) {
+  Common c = make_common(S, L, work);
+  for (auto it = S.panels.rbegin(); it != S.panels.rend(); ++it) {
+    PanelK k = panel_args(S, *it);
+    if (k.nb > 0) {
+      const int nt = (k.nb + TM - 1) / TM;
+      hipLaunchKernelGGL(k_lhat, dim3(nt, nshift), dim3(NT), 0, st, c, k);
+      hipLaunchKernelGGL(k_selinv_off, dim3(nt, nshift), dim3(NT), 0, st, c, k);
+      hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, nshift), dim3(NT), 0, st, c, k);
+    }
+    hipLaunchKernelGGL(k_selinv_diag_final, dim3(1, nshift), dim3(NT), 0, st, c, k);
+    PXS_CHECK_LAUNCH();
+  }
+  return 0;
+}
+
+int run_pole_sum(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
+                 const double* Sv, int nsets, const double* weights_host, double* out,
+                 hipStream_t st) {
+  char* w = (char*)work;
+  hipError_t e = hipMemcpyAsync(w + WK_WEIGHTS, weights_host, sizeof(double) * 2 * nsets * nshift,
+                                hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return (int)e;
+  const char* m = (const char*)S.dmaps;
+  const int nb = blocks_for(S.nnz_lower, POLESUM_BLOCKS);
+  hipLaunchKernelGGL(k_pole_sum, dim3(nb), dim3(NT), 0, st, (const double*)L, S.nnzL_store, nshift,
+                     (const double*)(w + WK_WEIGHTS), nsets, (const int64_t*)(m + S.o_entry_off),
+                     (const int32_t*)(m + S.o_entry_diag), S.nnz_lower, H, Sv, out,
+                     (double*)(w + WK_POLESUM_PART));
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)(w + WK_POLESUM_PART), nb,
+                     (double*)(w + WK_TRACES));
+  PXS_CHECK_LAUNCH();
+  return 0;
+}
+
+int run_gather(const Symbolic& S, int shift, const void* L, void* out, hipStream_t st) {
+  const char* m = (const char*)S.dmaps;
+  const double* Ls = (const double*)L + 2 * S.nnzL_store * (int64_t)shift;
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(S.nnz_lower, 4096)), dim3(NT), 0, st, Ls,
+                     (const int64_t*)(m + S.o_entry_off), S.nnz_lower, (double2*)out);
+  PXS_CHECK_LAUNCH();
+  return 0;
+}
+
+int run_get_diag(const Symbolic& S, int shift, bool cplx, const void* L, void* out, hipStream_t st) {
+  const char* m = (const char*)S.dmaps;
+  const double* Ls = (const double*)L + (cplx ? 2 : 1) * S.nnzL_store * (int64_t)shift;
+  hipLaunchKernelGGL(k_get_diag, dim3((S.n + NT - 1) / NT), dim3(NT), 0, st, Ls,
+                     (const int64_t*)(m + S.o_diagoff), S.n, cplx ? 1 : 0, (double2*)out);
+  PXS_CHECK_LAUNCH();
+  return 0;
+}
+
+}  // namespace pxs

@@ -1,0 +1,91 @@
+// Internal data structures shared by the host analysis, the launch code and
+// the C ABI.  Not installed; the public interface is include/pexsi_hip.h.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace pxs {
+
+// Pole table (poles.cpp).  shifts_ri: 2*P doubles, weights_ri: 2*nsets*P.
+int pole_table(double beta, double dE, double mu, int P, int nsets, double* shifts_ri,
+               double* weights_ri);
+
+struct Panel {
+  int32_t J;   // supernode
+  int32_t p0;  // first column, as a position in the supernode's row list
+  int32_t wp;  // width
+  int32_t nb_rows;  // rows below the panel's diagonal block (= ld_J - p0 - wp)
+};
+
+// Result of the symbolic analysis (symbolic.cpp).  All indices are 0-based;
+// "new" indices are positions after the fill-reducing permutation.
+struct Symbolic {
+  int32_t n = 0;
+  int64_t nnz_lower = 0;
+  int32_t panel_width = 64;
+  double pivot_tol = 1e-14;
+
+  std::vector<int32_t> perm;   // new -> old column
+  std::vector<int32_t> iperm;  // old -> new column
+
+  // Supernodes: columns [sfirst[J], sfirst[J+1]) in the new order.
+  int32_t nsuper = 0;
+  std::vector<int32_t> sfirst;
+  std::vector<int32_t> sparent;          // -1 for roots
+  std::vector<int64_t> rowptr;           // row list E_J = rows[rowptr[J] .. rowptr[J+1])
+  std::vector<int32_t> rows;             // own columns first, then the rows below
+  std::vector<int64_t> off;              // storage offset (elements) of supernode J
+  std::vector<int32_t> ld;               // leading dimension = |E_J|
+  std::vector<int32_t> snode_of_col;     // new column -> supernode
+  int64_t nnzL_store = 0;                // sum ld_J * w_J
+  int64_t nnzL_stored_lower = 0;         // sum over J of lower part incl. diagonal
+  int64_t nnzL_exact = 0;
+  double flops_factor = 0.0, flops_selinv = 0.0;
+  int32_t max_front = 0;
+
+  // Gather/scatter maps (host copies, uploaded by pxs_symbolic_bind).
+  //   address of element (row position i, column position q) of supernode
+  //   J's row list, i >= q:  colmap[rowptr[J] + q] + relpos[colseg[rowptr[J] + q] + i]
+  std::vector<int64_t> colmap;
+  std::vector<int64_t> colseg;
+  std::vector<int32_t> relpos;
+  std::vector<int64_t> entry_off;    // input entry -> element offset
+  std::vector<int32_t> entry_diag;   // 1 on the diagonal, else 0
+
+  std::vector<Panel> panels;        // factor order; selected inversion runs backwards
+  int64_t max_below = 0;            // max nb_rows over panels
+  int32_t max_split = 1;            // split-K pieces of the diagonal SelInv update
+
+  // Device copies (inside the caller's map buffer).
+  void* dmaps = nullptr;
+  int64_t map_bytes = 0;
+  int64_t o_colmap = 0, o_colseg = 0, o_entry_off = 0, o_relpos = 0, o_entry_diag = 0, o_diagoff = 0;
+  std::vector<int64_t> diagoff;     // new column -> element offset of its diagonal entry
+
+  // Workspace layout per batch.
+  int64_t work_fixed = 0, work_per_shift = 0;
+};
+
+struct AnalyzeOptions {
+  int ordering = 0;
+  int leaf_cols = 128;
+  int panel_width = 64;
+  double pivot_tol = 1e-14;
+};
+
+// Returns 0 on success, -1 on invalid input (msg set).
+int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nblk,
+            const int32_t* blkptr, const double* coords, const AnalyzeOptions& opt,
+            Symbolic& S, std::string& msg);
+
+// Number of split-K pieces used by the diagonal-block SelInv update of a panel
+// with `below` rows beneath it.
+inline int32_t split_count(int64_t below) {
+  const int64_t chunk = 512;
+  int64_t s = (below + chunk - 1) / chunk;
+  if (s < 1) s = 1;
+  return (int32_t)s;
+}
+
+}  // namespace pxs

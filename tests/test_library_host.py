@@ -1,0 +1,182 @@
+"""Host-side checks of the C-ABI library (no GPU): the library loads and
+exports every declared entry point; its pole table matches the oracle's;
+its symbolic analysis contains the exact pattern of L (brute-force oracle)
+and obeys eq. parent at supernode level; malformed input is rejected."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import poles as opoles
+from oracle import symbolic as osym
+from paper_1405_0194_amd import binding as B
+from paper_1405_0194_amd import lattice
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(pxs_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    names = _declared()
+    assert len(names) >= 14
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("beta,dE,mu,P", [(lattice.BETA_300K, 2.0, 0.1, 40),
+                                          (lattice.BETA_300K, 1.05, -0.05, 80),
+                                          (100.0, 3.0, 0.5, 20), (5000.0, 1.0, 0.0, 60)])
+def test_pole_table_matches_oracle(beta, dE, mu, P):
+    sh, wt = B.poles(beta, dE, mu, P, 4)
+    osh, ow = opoles.pole_table(beta, dE, mu, P)
+    scale = np.abs(osh - mu).max()
+    assert np.abs(sh - osh).max() <= 1e-11 * scale
+    for g, name in enumerate(opoles.SETS):
+        assert np.abs(wt[g] - ow[name]).max() <= 1e-11 * np.abs(ow[name]).max(), name
+    assert np.all(sh.imag > 0)
+
+
+def test_pole_table_rejects_bad_arguments():
+    with pytest.raises(B.PxsError):
+        B.poles(1000.0, 1.0, 0.0, 41)
+    with pytest.raises(B.PxsError):
+        B.poles(-1.0, 1.0, 0.0, 40)
+    with pytest.raises(B.PxsError):
+        B.poles(1000.0, 1.0, 0.0, 40, nsets=5)
+
+
+def _lower_csc_from_dense(P):
+    n = P.shape[0]
+    colptr = [0]
+    rows = []
+    for j in range(n):
+        r = [i for i in range(j, n) if P[i, j]]
+        rows += r
+        colptr.append(len(rows))
+    return np.array(colptr, dtype=np.int64), np.array(rows, dtype=np.int32)
+
+
+def _check_symbolic(a, Pfull):
+    ex = a.export()
+    n = Pfull.shape[0]
+    perm = ex["perm"]
+    assert sorted(perm.tolist()) == list(range(n))
+    Lx = osym.fill_pattern(osym.permute(Pfull, perm))       # exact pattern, new order
+    sp, rp, rows, par = ex["super_ptr"], ex["row_ptr"], ex["rows"], ex["parent"]
+    ns = sp.shape[0] - 1
+    owner = np.zeros(n, dtype=np.int64)
+    for J in range(ns):
+        owner[sp[J]:sp[J + 1]] = J
+    for J in range(ns):
+        E = rows[rp[J]:rp[J + 1]]
+        w = sp[J + 1] - sp[J]
+        assert np.array_equal(E[:w], np.arange(sp[J], sp[J + 1]))
+        assert np.all(np.diff(E) > 0)
+        Eset = set(E.tolist())
+        for j in range(sp[J], sp[J + 1]):
+            need = np.nonzero(Lx[j:, j])[0] + j
+            assert set(need.tolist()) <= Eset, (J, j)
+        below = E[w:]
+        # eq. parent at supernode level: the owner of the first row below
+        assert par[J] == (owner[below[0]] if below.size else -1)
+    return Lx
+
+
+@pytest.mark.parametrize("ordering", [0, 1])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_symbolic_contains_exact_pattern_random(seed, ordering):
+    rng = np.random.default_rng(seed)
+    n = 60
+    P = rng.uniform(size=(n, n)) < 0.05
+    P = P | P.T | np.eye(n, dtype=bool)
+    colptr, rows = _lower_csc_from_dense(P)
+    a = B.Analysis(n, colptr, rows, ordering=ordering, leaf_cols=8, panel_width=5)
+    Lx = _check_symbolic(a, P)
+    # without blocks the exact counts are exact at column level
+    ck = Lx.sum(axis=0) - 1
+    assert a.info["nnz_L_exact"] == int(Lx.sum())
+    assert a.info["flops_factor"] == pytest.approx(8.0 * np.sum(ck * (ck + 1) / 2.0))
+    assert a.info["flops_selinv"] == pytest.approx(8.0 * np.sum(ck * ck + ck))
+
+
+def test_symbolic_chain_with_blocks_and_coords():
+    s = lattice.config_system(0)
+    a = B.Analysis.from_system(s, leaf_cols=16)
+    P = osym.dense_pattern_from_lower_csc(s.n, s.colptr, s.rowind)
+    Lx = _check_symbolic(a, P)
+    assert a.info["nnz_L_exact"] == int(Lx.sum())
+    assert a.info["nsuper"] > 3
+
+
+def test_symbolic_small_honeycomb_graph_ordering():
+    s = lattice.make_system("honeycomb", (4, 3), 3, 3.0, 5, periodic=False)
+    a = B.Analysis(s.n, s.colptr, s.rowind, blkptr=s.blkptr, leaf_cols=9)
+    P = osym.dense_pattern_from_lower_csc(s.n, s.colptr, s.rowind)
+    Lx = _check_symbolic(a, P)
+    assert a.info["nnz_L_exact"] == int(Lx.sum())
+
+
+def test_nested_dissection_reduces_fill_on_grid():
+    # 2D grid: nested dissection must beat the natural (banded) order
+    s = lattice.make_system("cubic", (16, 16, 1), 1, 1.0, 9, periodic=False)
+    nd = B.Analysis.from_system(s, leaf_cols=8)
+    nat = B.Analysis.from_system(s, ordering=1)
+    assert nd.info["nnz_L_exact"] < nat.info["nnz_L_exact"]
+    assert nd.info["flops_factor"] < nat.info["flops_factor"]
+
+
+def test_fill_growth_slopes_1d_2d_3d():
+    # Sec. II.A: nnz(L) grows like N (1D), N^1.5 (2D), N^2 (3D) -- check
+    # that the measured log-log slopes are ordered and near those values
+    def slope(kind, dims_list, orb):
+        xs, ys = [], []
+        for d in dims_list:
+            s = lattice.make_system(kind, d, orb, 1.0 if kind != "chain" else 1.0, 3, periodic=False)
+            a = B.Analysis.from_system(s, leaf_cols=8)
+            xs.append(np.log(s.n))
+            ys.append(np.log(a.info["nnz_L_exact"]))
+        return np.polyfit(xs, ys, 1)[0]
+    s1 = slope("chain", [200, 400, 800, 1600], 1)
+    s2 = slope("cubic", [(12, 12, 1), (24, 24, 1), (48, 48, 1)], 1)
+    s3 = slope("cubic", [(6, 6, 6), (9, 9, 9), (12, 12, 12)], 1)
+    assert 0.9 < s1 < 1.15
+    assert 1.1 < s2 < 1.6
+    assert 1.4 < s3 < 2.1
+    assert s1 < s2 < s3
+
+
+@pytest.mark.parametrize("bad", ["unsorted", "nodiag", "upper", "range"])
+def test_analyze_rejects_malformed_csc(bad):
+    colptr = np.array([0, 2, 4, 5], dtype=np.int64)
+    rows = np.array([0, 2, 1, 2, 2], dtype=np.int32)
+    if bad == "unsorted":
+        rows = np.array([0, 2, 2, 1, 2], dtype=np.int32)
+    elif bad == "nodiag":
+        rows = np.array([1, 2, 1, 2, 2], dtype=np.int32)
+    elif bad == "upper":
+        rows = np.array([0, 2, 0, 1, 2], dtype=np.int32)
+    elif bad == "range":
+        rows = np.array([0, 3, 1, 2, 2], dtype=np.int32)
+    with pytest.raises(B.PxsError) as ei:
+        B.Analysis(3, colptr, rows)
+    assert ei.value.code == B.PXS_EINVAL
+
+
+def test_analyze_rejects_bad_blocks():
+    colptr = np.array([0, 1, 2, 3], dtype=np.int64)
+    rows = np.array([0, 1, 2], dtype=np.int32)
+    with pytest.raises(B.PxsError):
+        B.Analysis(3, colptr, rows, blkptr=np.array([0, 2, 2, 3]))
+    with pytest.raises(B.PxsError):
+        B.Analysis(3, colptr, rows, blkptr=np.array([0, 1, 4]))
