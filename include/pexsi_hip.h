@@ -187,6 +187,19 @@ pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double
                               int64_t* info, pxs_c64* shifts, pxs_c64* weights,
                               void* stream);
 
+/* Kernel timing for benchmarks: while a profile is open, every launch of the
+ * selected kernel class is bracketed by HIP events on its launch stream.
+ * kernel: 1 factor update, 2 SelInv off-diagonal product, 3 panel TRSM,
+ *         4 SelInv diagonal-block product, 5 L-hat product, 6 diagonal-block
+ *         LDL^T, 7 assembly, 8 pole sum.
+ * pxs_profile_end synchronises those events and returns the summed kernel
+ * time (ms), the number of launches and their algorithmic flops (complex
+ * multiply-add = 8 flops, on the stored supernodal structure, no tile
+ * padding) or, for kernels 7 and 8, their algorithmic HBM bytes.
+ * Process-wide state; not thread safe.  PXS_ESTATE if no profile is open. */
+pxs_status pxs_profile_begin(int32_t kernel);
+pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work);
+
 /* Text of the last HIP or validation error seen by this thread (diagnostics). */
 const char* pxs_last_error(void);
 

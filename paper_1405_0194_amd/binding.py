@@ -69,6 +69,8 @@ def load():
         "pxs_inertia": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
         "pxs_density_matrix": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
                                          C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
+        "pxs_profile_begin": (C.c_int, [C.c_int32]),
+        "pxs_profile_end": (C.c_int, [_P, _P, _P]),
         "pxs_free_symbolic": (None, [_P]),
         "pxs_free_numeric": (None, [_P]),
         "pxs_status_string": (C.c_char_p, [C.c_int]),
@@ -292,3 +294,21 @@ def density_matrix(analysis: Analysis, H, S, beta, dE, mu, P, nsets=2, L=None, w
                                   _stream(stream))
     _check("pxs_density_matrix", code, allow=(PXS_OK, PXS_TINY_PIVOT))
     return out.view(nsets, nnz), tr.reshape(nsets, 2), info, sh, wt.reshape(nsets, P)
+
+
+KERNELS = {"update": 1, "selinv_off": 2, "trsm": 3, "selinv_diag": 4, "lhat": 5, "diag": 6,
+           "assemble": 7, "pole_sum": 8}
+
+
+def profile_begin(kernel: str):
+    """Starts HIP-event timing of one kernel class inside the library."""
+    _check("pxs_profile_begin", load().pxs_profile_begin(KERNELS[kernel]))
+
+
+def profile_end():
+    """Returns (total kernel ms, launches, algorithmic flops or bytes)."""
+    ms = C.c_double()
+    n = C.c_int64()
+    w = C.c_double()
+    _check("pxs_profile_end", load().pxs_profile_end(C.byref(ms), C.byref(n), C.byref(w)))
+    return ms.value, n.value, w.value

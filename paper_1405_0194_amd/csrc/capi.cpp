@@ -315,6 +315,19 @@ pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double
   return piv;
 }
 
+pxs_status pxs_profile_begin(int32_t kernel) {
+  if (kernel < 1 || kernel > 8) return PXS_EINVAL;
+  pxs::profile_begin(kernel);
+  return PXS_OK;
+}
+
+pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work) {
+  if (!total_ms || !launches || !work) return PXS_EINVAL;
+  int e = pxs::profile_end(total_ms, launches, work);
+  if (e != 0) return hip_fail(e);
+  return PXS_OK;
+}
+
 void pxs_free_symbolic(pxs_symbolic sym) { delete sym; }
 void pxs_free_numeric(pxs_numeric num) { delete num; }
 

@@ -22,6 +22,12 @@ constexpr int64_t WK_NEGC = WK_INFO + 8 * MAX_SHIFTS;   // MAX_SHIFTS int64
 constexpr int64_t WK_WEIGHTS = 262144;       // 4 x MAX_SHIFTS complex
 constexpr int64_t WK_FIXED_BYTES = 1 << 20;
 
+// kernel-class timing with HIP events (pxs_profile_begin / _end)
+enum KernelClass { KC_NONE = 0, KC_UPDATE = 1, KC_SELINV_OFF = 2, KC_TRSM = 3, KC_SELINV_DIAG = 4,
+                   KC_LHAT = 5, KC_DIAG = 6, KC_ASSEMBLE = 7, KC_POLESUM = 8 };
+int profile_begin(int kernel);
+int profile_end(double* ms, int64_t* launches, double* work);
+
 template <bool CPLX>
 int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
                const double* shifts_host, void* L, void* work, hipStream_t st);

@@ -694,6 +694,38 @@ __global__ void k_get_diag(const double* __restrict__ L, const int64_t* __restri
 // --------------------------------------------------------------------------
 namespace {
 
+// Event pairs around the launches of one kernel class (benchmarks only).
+struct Profiler {
+  int kernel = KC_NONE;
+  std::vector<hipEvent_t> ev;   // pool, reused across profiles
+  size_t used = 0;
+  int64_t launches = 0;
+  double work = 0.0;
+};
+Profiler g_prof;
+
+struct ProfScope {
+  hipStream_t st;
+  bool on;
+  int err = 0;
+  ProfScope(int kernel, hipStream_t s, double work) : st(s), on(g_prof.kernel == kernel && kernel != KC_NONE) {
+    if (!on) return;
+    while (g_prof.ev.size() < g_prof.used + 2) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) { on = false; err = 1; return; }
+      g_prof.ev.push_back(e);
+    }
+    hipEventRecord(g_prof.ev[g_prof.used], st);
+    g_prof.launches += 1;
+    g_prof.work += work;
+  }
+  ~ProfScope() {
+    if (!on) return;
+    hipEventRecord(g_prof.ev[g_prof.used + 1], st);
+    g_prof.used += 2;
+  }
+};
+
 inline int blocks_for(int64_t n, int cap) {
   int64_t b = (n + NT - 1) / NT;
   if (b < 1) b = 1;
@@ -742,6 +774,32 @@ Common make_common(const Symbolic& S, void* L, void* work) {
     if (e_ != hipSuccess) return (int)e_;          \
   } while (0)
 
+int profile_begin(int kernel) {
+  g_prof.kernel = kernel;
+  g_prof.used = 0;
+  g_prof.launches = 0;
+  g_prof.work = 0.0;
+  return 0;
+}
+
+int profile_end(double* ms, int64_t* launches, double* work) {
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
+    hipError_t e = hipEventSynchronize(g_prof.ev[i + 1]);
+    if (e != hipSuccess) return (int)e;
+    float t = 0.0f;
+    e = hipEventElapsedTime(&t, g_prof.ev[i], g_prof.ev[i + 1]);
+    if (e != hipSuccess) return (int)e;
+    tot += t;
+  }
+  *ms = tot;
+  *launches = g_prof.launches;
+  *work = g_prof.work;
+  g_prof.kernel = KC_NONE;
+  g_prof.used = 0;
+  return 0;
+}
+
 template <bool CPLX>
 int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
                const double* shifts_host, void* L, void* work, hipStream_t st) {
@@ -766,17 +824,31 @@ int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
   if (total_d & 1)
     hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(64), 0, st, (double2*)((double*)L + total_d - 2), (int64_t)1);
   PXS_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_assemble<CPLX>, dim3(blocks_for(S.nnz_lower, 2048), nshift), dim3(NT), 0, st,
-                     (double*)L, S.nnzL_store, H, Sv, eoff, S.nnz_lower, (const double*)(w + WK_SHIFTS));
+  {
+    // bytes: H, S, offsets read once per shift block; one element written per entry and shift
+    ProfScope ps(KC_ASSEMBLE, st, (double)S.nnz_lower * (24.0 + (CPLX ? 16.0 : 8.0) * nshift));
+    hipLaunchKernelGGL(k_assemble<CPLX>, dim3(blocks_for(S.nnz_lower, 2048), nshift), dim3(NT), 0, st,
+                       (double*)L, S.nnzL_store, H, Sv, eoff, S.nnz_lower, (const double*)(w + WK_SHIFTS));
+  }
   PXS_CHECK_LAUNCH();
   Common c = make_common(S, L, work);
+  const double fm = CPLX ? 8.0 : 2.0;   // flops per multiply-add
   for (const Panel& P : S.panels) {
     PanelK k = panel_args(S, P);
-    hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NT), 0, st, c, k);
+    {
+      ProfScope ps(KC_DIAG, st, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0);
+      hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NT), 0, st, c, k);
+    }
     if (k.nb > 0) {
       const int nt = (k.nb + TM - 1) / TM;
-      hipLaunchKernelGGL(k_trsm<CPLX>, dim3(nt, nshift), dim3(NT), 0, st, c, k);
-      hipLaunchKernelGGL(k_update<CPLX>, dim3(nt * (nt + 1) / 2, nshift), dim3(NT), 0, st, c, k);
+      {
+        ProfScope ps(KC_TRSM, st, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
+        hipLaunchKernelGGL(k_trsm<CPLX>, dim3(nt, nshift), dim3(NT), 0, st, c, k);
+      }
+      {
+        ProfScope ps(KC_UPDATE, st, fm * nshift * (double)k.nb * (k.nb + 1) / 2.0 * k.wp);
+        hipLaunchKernelGGL(k_update<CPLX>, dim3(nt * (nt + 1) / 2, nshift), dim3(NT), 0, st, c, k);
+      }
     }
     PXS_CHECK_LAUNCH();
   }
@@ -792,9 +864,18 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
     PanelK k = panel_args(S, *it);
     if (k.nb > 0) {
       const int nt = (k.nb + TM - 1) / TM;
-      hipLaunchKernelGGL(k_lhat, dim3(nt, nshift), dim3(NT), 0, st, c, k);
-      hipLaunchKernelGGL(k_selinv_off, dim3(nt, nshift), dim3(NT), 0, st, c, k);
-      hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, nshift), dim3(NT), 0, st, c, k);
+      {
+        ProfScope ps(KC_LHAT, st, 8.0 * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
+        hipLaunchKernelGGL(k_lhat, dim3(nt, nshift), dim3(NT), 0, st, c, k);
+      }
+      {
+        ProfScope ps(KC_SELINV_OFF, st, 8.0 * nshift * (double)k.nb * k.nb * k.wp);
+        hipLaunchKernelGGL(k_selinv_off, dim3(nt, nshift), dim3(NT), 0, st, c, k);
+      }
+      {
+        ProfScope ps(KC_SELINV_DIAG, st, 8.0 * nshift * (double)k.nb * k.wp * k.wp);
+        hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, nshift), dim3(NT), 0, st, c, k);
+      }
     }
     hipLaunchKernelGGL(k_selinv_diag_final, dim3(1, nshift), dim3(NT), 0, st, c, k);
     PXS_CHECK_LAUNCH();
@@ -811,6 +892,8 @@ int run_pole_sum(const Symbolic& S, int nshift, const void* L, void* work, const
   if (e != hipSuccess) return (int)e;
   const char* m = (const char*)S.dmaps;
   const int nb = blocks_for(S.nnz_lower, POLESUM_BLOCKS);
+  // bytes: one complex per entry and shift, offsets, flags, H, S, nsets outputs
+  ProfScope ps(KC_POLESUM, st, (double)S.nnz_lower * (16.0 * nshift + 28.0 + 8.0 * nsets));
   hipLaunchKernelGGL(k_pole_sum, dim3(nb), dim3(NT), 0, st, (const double*)L, S.nnzL_store, nshift,
                      (const double*)(w + WK_WEIGHTS), nsets, (const int64_t*)(m + S.o_entry_off),
                      (const int32_t*)(m + S.o_entry_diag), S.nnz_lower, H, Sv, out,
