@@ -66,7 +66,8 @@ typedef struct {
   int32_t ordering;     /* 0: nested dissection (default), 1: natural order */
   int32_t leaf_cols;    /* max columns of a nested-dissection leaf (0: 128) */
   int32_t panel_width;  /* columns per numeric panel, 1..64 (0: 64) */
-  int32_t reserved0;
+  int32_t selinv_chunk; /* shifts per selected-inversion pass (0: the whole
+                           batch); bounds the dense Z_CC workspace */
   double pivot_tol;     /* |d_k| < pivot_tol * (max|H| + |w| max|S|) flags a
                            tiny pivot (0: 1e-14) */
   double reserved1[3];
@@ -83,10 +84,12 @@ typedef struct {
                                   panel_width-wide column blocks) */
   int64_t bytes_per_shift;     /* factor storage per complex shift (bytes);
                                   a real (inertia) shift needs half */
-  int64_t work_bytes;          /* workspace for a batch of nshift shifts:
-                                  work_fixed + nshift * work_per_shift */
+  int64_t work_bytes;          /* workspace for one shift (pxs_workspace_size
+                                  gives it for a batch) */
   int64_t work_fixed;
   int64_t work_per_shift;
+  int64_t gather_per_shift;    /* dense Z_CC copy, per shift of a SelInv chunk */
+  int64_t selinv_chunk;        /* as in pxs_options (0: whole batch) */
   int64_t map_bytes;           /* device bytes of the symbolic maps */
   int64_t max_front;           /* largest row count of a supernode */
   double flops_factor;         /* algorithmic flops per complex shift:
@@ -125,6 +128,11 @@ pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind,
 
 pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info);
 
+/* Workspace bytes for a batch of nshift shifts: work_fixed + nshift *
+ * work_per_shift, plus min(nshift, selinv_chunk or nshift) * gather_per_shift
+ * unless `real` (inertia batches run no selected inversion). */
+pxs_status pxs_workspace_size(pxs_symbolic sym, int32_t nshift, int32_t real, int64_t* bytes);
+
 /* Export of the analysis, for tests and tools (host arrays, any may be NULL):
  * perm[n] (new -> old column), super_ptr[nsuper+1] (first new column of each
  * supernode), super_parent[nsuper] (-1 for roots), row_ptr[nsuper+1] and
@@ -144,8 +152,9 @@ pxs_status pxs_symbolic_bind(pxs_symbolic sym, void* maps, void* stream);
  * Hval, Sval (device, nnz_lower doubles): values on the input pattern.
  * shifts (host, nshift): complex shifts w_l; Im w_l > 0 guarantees that
  *   the factorization exists (Im A_l is negative definite).
- * Lbuf (device, nshift * bytes_per_shift), work (device, work_fixed +
- *   nshift * work_per_shift): caller buffers, kept by the numeric handle.
+ * Lbuf (device, nshift * bytes_per_shift), work (device,
+ *   pxs_workspace_size(sym, nshift, 0) bytes): caller buffers, 256-byte
+ *   aligned, kept by the numeric handle.
  * info (host, nshift, nullable): 0, or the 1-based new column index of the
  *   first pivot below the threshold (the factor continues regardless).
  * Returns PXS_TINY_PIVOT if any info[l] != 0 (then synchronises stream). */

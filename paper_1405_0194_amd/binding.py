@@ -31,7 +31,7 @@ class c64(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("ordering", C.c_int32), ("leaf_cols", C.c_int32), ("panel_width", C.c_int32),
-                ("reserved0", C.c_int32), ("pivot_tol", C.c_double), ("reserved1", C.c_double * 3)]
+                ("selinv_chunk", C.c_int32), ("pivot_tol", C.c_double), ("reserved1", C.c_double * 3)]
 
 
 class SymInfo(C.Structure):
@@ -39,6 +39,7 @@ class SymInfo(C.Structure):
                 ("nnz_L_exact", C.c_int64), ("nsuper", C.c_int64), ("npanel", C.c_int64),
                 ("bytes_per_shift", C.c_int64), ("work_bytes", C.c_int64),
                 ("work_fixed", C.c_int64), ("work_per_shift", C.c_int64),
+                ("gather_per_shift", C.c_int64), ("selinv_chunk", C.c_int64),
                 ("map_bytes", C.c_int64), ("max_front", C.c_int64),
                 ("flops_factor", C.c_double), ("flops_selinv", C.c_double)]
 
@@ -59,6 +60,7 @@ def load():
         "pxs_poles": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, _P, _P]),
         "pxs_analyze": (C.c_int, [C.c_int32, _P, _P, C.c_int32, _P, _P, _P, _P]),
         "pxs_symbolic_info": (C.c_int, [_P, _P]),
+        "pxs_workspace_size": (C.c_int, [_P, C.c_int32, C.c_int32, _P]),
         "pxs_symbolic_export": (C.c_int, [_P, _P, _P, _P, _P, _P]),
         "pxs_symbolic_bind": (C.c_int, [_P, _P, _P]),
         "pxs_factor": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
@@ -121,13 +123,13 @@ class Analysis:
     """Symbolic analysis handle (host), optionally bound to device maps."""
 
     def __init__(self, n, colptr, rowind, blkptr=None, coords=None, ordering=0, leaf_cols=0,
-                 panel_width=0, pivot_tol=0.0):
+                 panel_width=0, pivot_tol=0.0, selinv_chunk=0):
         lib = load()
         self._lib = lib
         self.n = int(n)
         colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         rowind = np.ascontiguousarray(rowind, dtype=np.int32)
-        opt = Options(ordering, leaf_cols, panel_width, 0, pivot_tol)
+        opt = Options(ordering, leaf_cols, panel_width, selinv_chunk, pivot_tol)
         h = _P()
         nblk = 0
         bp = None
@@ -180,9 +182,13 @@ class Analysis:
         import torch
         per = self.info["bytes_per_shift"] // (2 if real else 1)
         L = torch.empty(per * nshift, dtype=torch.uint8, device=device)
-        W = torch.empty(self.info["work_fixed"] + nshift * self.info["work_per_shift"],
-                        dtype=torch.uint8, device=device)
+        W = torch.empty(self.workspace_size(nshift, real), dtype=torch.uint8, device=device)
         return L, W
+
+    def workspace_size(self, nshift, real=False):
+        b = C.c_int64()
+        _check("pxs_workspace_size", self._lib.pxs_workspace_size(self._h, nshift, int(real), C.byref(b)))
+        return b.value
 
     def __del__(self):
         try:

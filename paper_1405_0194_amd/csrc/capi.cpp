@@ -105,6 +105,8 @@ pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, 
     if (opt->leaf_cols > 0) o.leaf_cols = opt->leaf_cols;
     if (opt->panel_width > 0) o.panel_width = opt->panel_width;
     if (opt->pivot_tol > 0) o.pivot_tol = opt->pivot_tol;
+    if (opt->selinv_chunk < 0) return PXS_EINVAL;
+    o.selinv_chunk = opt->selinv_chunk;
     if (o.ordering != 0 && o.ordering != 1) return PXS_EINVAL;
     if (o.panel_width > 64) return PXS_EINVAL;
   }
@@ -140,11 +142,25 @@ pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info) {
   info->bytes_per_shift = 16 * S.nnzL_store;
   info->work_fixed = S.work_fixed;
   info->work_per_shift = S.work_per_shift;
-  info->work_bytes = S.work_fixed + S.work_per_shift;
+  info->work_bytes = S.work_fixed + S.work_per_shift + S.gather_per_shift;
+  info->gather_per_shift = S.gather_per_shift;
+  info->selinv_chunk = S.selinv_chunk;
   info->map_bytes = S.map_bytes;
   info->max_front = S.max_front;
   info->flops_factor = S.flops_factor;
   info->flops_selinv = S.flops_selinv;
+  return PXS_OK;
+}
+
+pxs_status pxs_workspace_size(pxs_symbolic sym, int32_t nshift, int32_t real, int64_t* bytes) {
+  if (!sym || !bytes || nshift < 1 || nshift > pxs::MAX_SHIFTS) return PXS_EINVAL;
+  const pxs::Symbolic& S = sym->S;
+  int64_t b = S.work_fixed + (int64_t)nshift * S.work_per_shift;
+  if (!real) {
+    const int32_t chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
+    b += (int64_t)chunk * S.gather_per_shift;
+  }
+  *bytes = b;
   return PXS_OK;
 }
 

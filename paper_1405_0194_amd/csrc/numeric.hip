@@ -156,31 +156,90 @@ __device__ __forceinline__ void acc_foreach(const Acc<CPLX>& acc, F f) {
       }
 }
 
-// Staging: fill (m or n, k) of one chunk from a functor get(idx, k) -> cplx.
-// FAST_K = false: consecutive threads take consecutive idx (memory contiguous
-// along idx); FAST_K = true: consecutive threads take consecutive k.
-template <bool CPLX, bool FAST_K, class G>
-__device__ __forceinline__ void stage_op(double (*re)[LDP], double (*im)[LDP], G get) {
+// Staging of one k-chunk.  slot(j) gives the (idx, k) pair that thread t
+// moves in its j-th of four transfers: FAST_K = false puts consecutive
+// threads on consecutive idx (memory contiguous along idx), FAST_K = true on
+// consecutive k.  fetch() reads global memory into registers, commit()
+// writes the registers to LDS, so the next chunk's loads can be in flight
+// while the current chunk runs on the matrix cores.
+template <bool FAST_K>
+__device__ __forceinline__ void slot(int j, int& ii, int& kk) {
   const int t = threadIdx.x;
-  cplx v[4];
-  int ii[4], kk[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (!FAST_K) {
-      ii[j] = t & 63;
-      kk[j] = (t >> 6) + 4 * j;
-    } else {
-      kk[j] = t & 15;
-      ii[j] = (t >> 4) + 16 * j;
-    }
-    v[j] = get(ii[j], kk[j]);
-  }
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    re[kk[j]][ii[j]] = v[j].re;
-    if (CPLX) im[kk[j]][ii[j]] = v[j].im;
+  if (!FAST_K) {
+    ii = t & 63;
+    kk = (t >> 6) + 4 * j;
+  } else {
+    kk = t & 15;
+    ii = (t >> 4) + 16 * j;
   }
 }
+
+template <bool FAST_K, class G>
+__device__ __forceinline__ void fetch(cplx (&v)[4], int k0, G get) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int ii, kk;
+    slot<FAST_K>(j, ii, kk);
+    v[j] = get(ii, k0 + kk);
+  }
+}
+
+template <bool CPLX, bool FAST_K>
+__device__ __forceinline__ void commit(double (*re)[LDP], double (*im)[LDP], const cplx (&v)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int ii, kk;
+    slot<FAST_K>(j, ii, kk);
+    re[kk][ii] = v[j].re;
+    if (CPLX) im[kk][ii] = v[j].im;
+  }
+}
+
+template <class G>
+__device__ __forceinline__ void fetch_rt(cplx (&v)[4], int k0, G get, bool fast) {
+  if (fast) fetch<true>(v, k0, get);
+  else fetch<false>(v, k0, get);
+}
+template <bool CPLX>
+__device__ __forceinline__ void commit_rt(double (*re)[LDP], double (*im)[LDP], const cplx (&v)[4], bool fast) {
+  if (fast) commit<CPLX, true>(re, im, v);
+  else commit<CPLX, false>(re, im, v);
+}
+
+// Software-pipelined K loop over [kb, ke): P += A[:, k] B[k, :].  ga(m, k)
+// and gb(n, k) return the operands (zero outside the matrices); bfast(k0)
+// picks the B staging order per chunk (uniform across the workgroup).
+template <bool CPLX, bool AFAST, class GA, class GB, class BF>
+__device__ __forceinline__ void gemm_pipe(Acc<CPLX>& acc, Stage<CPLX>& s, int kb, int ke, GA ga, GB gb,
+                                          BF bfast) {
+  cplx ra[4], rb[4];
+  bool fb = false;
+  if (kb < ke) {
+    fb = bfast(kb);
+    fetch<AFAST>(ra, kb, ga);
+    fetch_rt(rb, kb, gb, fb);
+  }
+  for (int k0 = kb; k0 < ke; k0 += KC) {
+    __syncthreads();
+    commit<CPLX, AFAST>(s.a_re, s.a_im, ra);
+    commit_rt<CPLX>(s.b_re, s.b_im, rb, fb);
+    __syncthreads();
+    const int k1 = k0 + KC;
+    if (k1 < ke) {
+      fb = bfast(k1);
+      fetch<AFAST>(ra, k1, ga);
+      fetch_rt(rb, k1, gb, fb);
+    }
+    mfma_chunk<CPLX>(acc, s);
+  }
+}
+
+struct RowsFast {
+  __device__ bool operator()(int) const { return false; }
+};
+struct KFast {
+  __device__ bool operator()(int) const { return true; }
+};
 
 // --------------------------------------------------------------------------
 // small kernels
@@ -258,6 +317,9 @@ struct PanelK {
   int32_t nb;      // rows below the panel's diagonal block
   int32_t col0;    // new index of the panel's first column
   int32_t split;   // split-K pieces (SelInv diagonal update)
+  int32_t w;       // width of the supernode
+  int32_t c;       // rows below the supernode (ld - w)
+  int32_t sh0;     // first shift of this launch (grid.y counts from it)
 };
 
 struct Common {
@@ -274,6 +336,8 @@ struct Common {
   int64_t* info;           // device, per shift
   int64_t* negc;           // device, per shift
   double pivtol;
+  double* G;               // dense Z_CC of the current supernode, per shift of a chunk
+  int64_t gstride;         // doubles per shift in G
 };
 
 template <bool CPLX>
@@ -380,27 +444,60 @@ __global__ void __launch_bounds__(NT) k_trsm(Common c, PanelK p) {
   }
   Acc<CPLX> acc;
   acc.zero();
-  for (int k0 = 0; k0 < p.wp; k0 += KC) {
-    __syncthreads();
-    // A operand: Linv[c][k] (column k of the diagonal block, rows c)
-    stage_op<CPLX, false>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
-      const int kg = k0 + k;
-      if (m >= p.wp || kg >= p.wp || m < kg) return cplx{0.0, 0.0};
-      if (m == kg) return cplx{1.0, 0.0};
-      return ld_elem<CPLX>(Ls, dbase + (int64_t)kg * p.ld + m);
-    });
-    // B operand: A[i][k]
-    stage_op<CPLX, false>(s.b_re, s.b_im, [&](int n, int k) -> cplx {
-      const int kg = k0 + k, ig = i0 + n;
-      if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
-      return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
-    });
-    __syncthreads();
-    mfma_chunk<CPLX>(acc, s);
-  }
+  gemm_pipe<CPLX, false>(
+      acc, s, 0, p.wp,
+      [&](int m, int kg) -> cplx {   // Linv[c][k]: column k of the diagonal block
+        if (m >= p.wp || kg >= p.wp || m < kg) return cplx{0.0, 0.0};
+        if (m == kg) return cplx{1.0, 0.0};
+        return ld_elem<CPLX>(Ls, dbase + (int64_t)kg * p.ld + m);
+      },
+      [&](int n, int kg) -> cplx {   // A[i][k]
+        const int ig = i0 + n;
+        if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
+        return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
+      },
+      RowsFast());
   acc_foreach<CPLX>(acc, [&](int m, int n, cplx v) {
     const int ig = i0 + n;
     if (m < p.wp && ig < p.nb) st_elem<CPLX>(Ls, rbase + (int64_t)m * p.ld + ig, cmul(v, dinv[m]));
+  });
+}
+
+// Left-looking update of panel p from the earlier columns of its own
+// supernode: A[r][c] -= sum_{k < p0} L[r][k] d_k L[c][k] for rows r >= p0 of
+// the row list and the panel's columns c.  P[c][r] = sum_k (d_k L[c][k]) L[r][k].
+template <bool CPLX>
+__global__ void __launch_bounds__(NT) k_int_update(Common c, PanelK p) {
+  __shared__ Stage<CPLX> s;
+  const int sh = blockIdx.y;
+  double* Ls = shift_base<CPLX>(c, sh);
+  const int r0 = blockIdx.x * TM;            // rows p0 + r0 .. of the row list
+  const int nrows = p.ld - p.p0;
+  const int64_t cbase = p.off + p.p0;        // element (row p0, column 0)
+  Acc<CPLX> acc;
+  acc.zero();
+  gemm_pipe<CPLX, false>(
+      acc, s, 0, p.p0,
+      [&](int m, int kg) -> cplx {   // d_k L[p0 + c][k]
+        if (m >= p.wp || kg >= p.p0) return cplx{0.0, 0.0};
+        const cplx d = ld_elem<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg);
+        return cmul(d, ld_elem<CPLX>(Ls, cbase + (int64_t)kg * p.ld + m));
+      },
+      [&](int n, int kg) -> cplx {   // L[p0 + r][k]
+        const int rg = r0 + n;
+        if (kg >= p.p0 || rg >= nrows) return cplx{0.0, 0.0};
+        return ld_elem<CPLX>(Ls, cbase + (int64_t)kg * p.ld + rg);
+      },
+      RowsFast());
+  acc_foreach<CPLX>(acc, [&](int m, int n, cplx v) {
+    const int rg = r0 + n;
+    if (m < p.wp && rg < nrows && rg >= m) {
+      const int64_t e = cbase + (int64_t)(p.p0 + m) * p.ld + rg;
+      cplx o = ld_elem<CPLX>(Ls, e);
+      o.re -= v.re;
+      o.im -= v.im;
+      st_elem<CPLX>(Ls, e, o);
+    }
   });
 }
 
@@ -413,38 +510,38 @@ __device__ __forceinline__ void tri_index(int b, int& ti, int& tj) {
   tj = b - x * (x + 1) / 2;
 }
 
-// A_BB -= L_Bp D L_Bp^T on lower tiles (ti >= tj), scattered through the maps.
+// Update of the rows/columns below columns [p0, p0 + wp) of a supernode:
+// A_BB -= L_B,K D_K L_B,K^T on lower tiles (ti >= tj), scattered through the
+// maps (B = row-list positions from p0 + wp on).  Used once per supernode
+// with K = all of its columns (p0 = 0, wp = w_J, B = the rows below it).
 // P[j][i] = sum_k (d_k L[j][k]) L[i][k].
 template <bool CPLX>
 __global__ void __launch_bounds__(NT) k_update(Common c, PanelK p) {
   __shared__ Stage<CPLX> s;
-  __shared__ cplx dk[64];
   const int sh = blockIdx.y;
   double* Ls = shift_base<CPLX>(c, sh);
   int ti, tj;
   tri_index(blockIdx.x, ti, tj);
   const int i0 = ti * TM, j0 = tj * TM;
-  const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;
-  const int64_t rbase = dbase + p.wp;
-  if (threadIdx.x < p.wp) dk[threadIdx.x] = ld_elem<CPLX>(Ls, dbase + (int64_t)threadIdx.x * p.ld + threadIdx.x);
+  const int base = p.p0 + p.wp;   // row-list position of the first row below
+  const int64_t rbase = p.off + base;   // element (row base, column 0)
+  const int kb = p.p0, ke = p.p0 + p.wp;
   Acc<CPLX> acc;
   acc.zero();
-  for (int k0 = 0; k0 < p.wp; k0 += KC) {
-    __syncthreads();
-    stage_op<CPLX, false>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
-      const int kg = k0 + k, jg = j0 + m;
-      if (kg >= p.wp || jg >= p.nb) return cplx{0.0, 0.0};
-      return cmul(dk[kg], ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + jg));
-    });
-    stage_op<CPLX, false>(s.b_re, s.b_im, [&](int n, int k) -> cplx {
-      const int kg = k0 + k, ig = i0 + n;
-      if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
-      return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
-    });
-    __syncthreads();
-    mfma_chunk<CPLX>(acc, s);
-  }
-  const int base = p.p0 + p.wp;   // row-list position of the first row below
+  gemm_pipe<CPLX, false>(
+      acc, s, kb, ke,
+      [&](int m, int kg) -> cplx {
+        const int jg = j0 + m;
+        if (kg >= ke || jg >= p.nb) return cplx{0.0, 0.0};
+        const cplx d = ld_elem<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg);
+        return cmul(d, ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + jg));
+      },
+      [&](int n, int kg) -> cplx {
+        const int ig = i0 + n;
+        if (kg >= ke || ig >= p.nb) return cplx{0.0, 0.0};
+        return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
+      },
+      RowsFast());
   const int64_t* cmap = c.colmap + p.cm;
   const int64_t* cseg = c.colseg + p.cm;
   acc_foreach<CPLX>(acc, [&](int m, int n, cplx v) {
@@ -470,7 +567,7 @@ __device__ __forceinline__ double* wbase(const Common& c, int sh) {
 // W = L_Bp Linv: P[c][i] = sum_k Linv[k][c] L[i][k]; W stored W[c * nb + i].
 __global__ void __launch_bounds__(NT) k_lhat(Common c, PanelK p) {
   __shared__ Stage<true> s;
-  const int sh = blockIdx.y;
+  const int sh = p.sh0 + blockIdx.y;
   double* Ls = shift_base<true>(c, sh);
   double* W = wbase(c, sh);
   const int i0 = blockIdx.x * TM;
@@ -478,64 +575,59 @@ __global__ void __launch_bounds__(NT) k_lhat(Common c, PanelK p) {
   const int64_t rbase = dbase + p.wp;
   Acc<true> acc;
   acc.zero();
-  for (int k0 = 0; k0 < p.wp; k0 += KC) {
-    __syncthreads();
-    // A[c][k] = Linv[k][c]: column c of the diagonal block, rows k (fast k)
-    stage_op<true, true>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
-      const int kg = k0 + k;
-      if (m >= p.wp || kg >= p.wp || kg < m) return cplx{0.0, 0.0};
-      if (kg == m) return cplx{1.0, 0.0};
-      return ld_elem<true>(Ls, dbase + (int64_t)m * p.ld + kg);
-    });
-    stage_op<true, false>(s.b_re, s.b_im, [&](int n, int k) -> cplx {
-      const int kg = k0 + k, ig = i0 + n;
-      if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
-      return ld_elem<true>(Ls, rbase + (int64_t)kg * p.ld + ig);
-    });
-    __syncthreads();
-    mfma_chunk<true>(acc, s);
-  }
+  gemm_pipe<true, true>(
+      acc, s, 0, p.wp,
+      [&](int m, int kg) -> cplx {   // Linv[k][c]: column c of the diagonal block, rows k
+        if (m >= p.wp || kg >= p.wp || kg < m) return cplx{0.0, 0.0};
+        if (kg == m) return cplx{1.0, 0.0};
+        return ld_elem<true>(Ls, dbase + (int64_t)m * p.ld + kg);
+      },
+      [&](int n, int kg) -> cplx {
+        const int ig = i0 + n;
+        if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
+        return ld_elem<true>(Ls, rbase + (int64_t)kg * p.ld + ig);
+      },
+      RowsFast());
   acc_foreach<true>(acc, [&](int m, int n, cplx v) {
     const int ig = i0 + n;
     if (m < p.wp && ig < p.nb) st_elem<true>(W, (int64_t)m * p.nb + ig, v);
   });
 }
 
-// Z_Bp = -Z_BB W: P[c][i] = sum_k W[k][c] Z(k, i), Z_BB gathered (symmetric).
+// Z_Bp = -Z_BB W: P[c][i] = sum_k W[k][c] Z(k, i).  Z_BB is symmetric; its
+// part inside the supernode's own columns is read from the supernode's
+// storage (column min(i, k), row max(i, k)), the part in the rows below it
+// from the dense copy G of Z_CC made by k_gather_cc.
 __global__ void __launch_bounds__(NT) k_selinv_off(Common c, PanelK p) {
   __shared__ Stage<true> s;
-  const int sh = blockIdx.y;
+  const int sh = p.sh0 + blockIdx.y;
   double* Ls = shift_base<true>(c, sh);
   const double* W = wbase(c, sh);
+  const double* G = c.G + c.gstride * blockIdx.y;
   const int i0 = blockIdx.x * TM;
   const int base = p.p0 + p.wp;
-  const int64_t* cmap = c.colmap + p.cm;
-  const int64_t* cseg = c.colseg + p.cm;
-  const int32_t* rel = c.relpos;
   Acc<true> acc;
   acc.zero();
-  for (int k0 = 0; k0 < p.nb; k0 += KC) {
-    __syncthreads();
-    stage_op<true, true>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
-      const int kg = k0 + k;
-      if (m >= p.wp || kg >= p.nb) return cplx{0.0, 0.0};
-      return ld_elem<true>(W, (int64_t)m * p.nb + kg);
-    });
-    auto getz = [&](int n, int k) -> cplx {
-      const int kg = k0 + k, ig = i0 + n;
-      if (kg >= p.nb || ig >= p.nb) return cplx{0.0, 0.0};
-      const int qk = base + kg, qi = base + ig;
-      const int64_t e = (qi >= qk) ? cmap[qk] + rel[cseg[qk] + qi] : cmap[qi] + rel[cseg[qi] + qk];
-      return ld_elem<true>(Ls, e);
-    };
-    if (k0 + KC <= i0 + 1) {
-      stage_op<true, false>(s.b_re, s.b_im, getz);   // all below the diagonal: rows contiguous
-    } else {
-      stage_op<true, true>(s.b_re, s.b_im, getz);    // above (or across) the diagonal
-    }
-    __syncthreads();
-    mfma_chunk<true>(acc, s);
-  }
+  gemm_pipe<true, true>(
+      acc, s, 0, p.nb,
+      [&](int m, int kg) -> cplx {
+        if (m >= p.wp || kg >= p.nb) return cplx{0.0, 0.0};
+        return ld_elem<true>(W, (int64_t)m * p.nb + kg);
+      },
+      [&](int n, int kg) -> cplx {
+        const int ig = i0 + n;
+        if (kg >= p.nb || ig >= p.nb) return cplx{0.0, 0.0};
+        const int qk = base + kg, qi = base + ig;
+        if (qk >= p.w && qi >= p.w) return ld_elem<true>(G, (int64_t)(qk - p.w) * p.c + (qi - p.w));
+        const int lo = min(qi, qk), hi = max(qi, qk);
+        return ld_elem<true>(Ls, p.off + (int64_t)lo * p.ld + hi);
+      },
+      // rows are contiguous for each k when the whole chunk lies on or below
+      // the diagonal of the tile, or inside G; otherwise k is contiguous
+      [&](int k0) -> bool {
+        const bool rows = (i0 >= k0 + KC - 1) || (base + k0 >= p.w && base + i0 >= p.w);
+        return !rows;
+      });
   const int64_t rbase = p.off + (int64_t)p.p0 * p.ld + base;
   acc_foreach<true>(acc, [&](int m, int n, cplx v) {
     const int ig = i0 + n;
@@ -543,10 +635,53 @@ __global__ void __launch_bounds__(NT) k_selinv_off(Common c, PanelK p) {
   });
 }
 
+// G = Z_CC: G[a + b c] = Z(w + a, w + b) for all a, b < c, from the
+// ancestors' storage through the maps (lower tiles read once, written to
+// both halves through an LDS transpose).
+__global__ void __launch_bounds__(NT) k_gather_cc(Common c, PanelK p) {
+  __shared__ double t_re[64][LDP];   // t[b][a]
+  __shared__ double t_im[64][LDP];
+  const int sh = p.sh0 + blockIdx.y;
+  const double* Ls = shift_base<true>(c, sh);
+  double* G = c.G + c.gstride * blockIdx.y;
+  int ta, tb;
+  tri_index(blockIdx.x, ta, tb);
+  const int a0 = ta * TM, b0 = tb * TM;
+  const int cc = p.c, w = p.w;
+  const int64_t* cmap = c.colmap + p.cm;
+  const int64_t* cseg = c.colseg + p.cm;
+  const int t = threadIdx.x;
+#pragma unroll 4
+  for (int j = 0; j < 16; ++j) {
+    const int la = t & 63, lb = (t >> 6) + 4 * j;
+    const int a = a0 + la, b = b0 + lb;
+    cplx v{0.0, 0.0};
+    if (a < cc && b < cc && a >= b) {
+      const int qa = w + a, qb = w + b;
+      v = ld_elem<true>(Ls, cmap[qb] + c.relpos[cseg[qb] + qa]);
+    }
+    t_re[lb][la] = v.re;
+    t_im[lb][la] = v.im;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int j = 0; j < 16; ++j) {
+    const int la = t & 63, lb = (t >> 6) + 4 * j;
+    const int a = a0 + la, b = b0 + lb;
+    if (a < cc && b < cc && a >= b) st_elem<true>(G, (int64_t)b * cc + a, cplx{t_re[lb][la], t_im[lb][la]});
+  }
+#pragma unroll 4
+  for (int j = 0; j < 16; ++j) {
+    const int lb = t & 63, la = (t >> 6) + 4 * j;
+    const int a = a0 + la, b = b0 + lb;
+    if (a < cc && b < cc && a > b) st_elem<true>(G, (int64_t)a * cc + b, cplx{t_re[lb][la], t_im[lb][la]});
+  }
+}
+
 // Partial W^T Z_Bp over k in [split * 512, ...): P[c][r] = sum_k Z[k][c] W[k][r].
 __global__ void __launch_bounds__(NT) k_selinv_diag_partial(Common c, PanelK p) {
   __shared__ Stage<true> s;
-  const int sh = blockIdx.y;
+  const int sh = p.sh0 + blockIdx.y;
   const int sp = blockIdx.x;
   double* Ls = shift_base<true>(c, sh);
   double* W = wbase(c, sh);
@@ -556,21 +691,17 @@ __global__ void __launch_bounds__(NT) k_selinv_diag_partial(Common c, PanelK p) 
   const int kb = sp * 512, ke = min(p.nb, kb + 512);
   Acc<true> acc;
   acc.zero();
-  for (int k0 = kb; k0 < ke; k0 += KC) {
-    __syncthreads();
-    stage_op<true, true>(s.a_re, s.a_im, [&](int m, int k) -> cplx {
-      const int kg = k0 + k;
-      if (m >= p.wp || kg >= ke) return cplx{0.0, 0.0};
-      return ld_elem<true>(Ls, rbase + (int64_t)m * p.ld + kg);
-    });
-    stage_op<true, true>(s.b_re, s.b_im, [&](int n, int k) -> cplx {
-      const int kg = k0 + k;
-      if (n >= p.wp || kg >= ke) return cplx{0.0, 0.0};
-      return ld_elem<true>(W, (int64_t)n * p.nb + kg);
-    });
-    __syncthreads();
-    mfma_chunk<true>(acc, s);
-  }
+  gemm_pipe<true, true>(
+      acc, s, kb, ke,
+      [&](int m, int kg) -> cplx {
+        if (m >= p.wp || kg >= ke) return cplx{0.0, 0.0};
+        return ld_elem<true>(Ls, rbase + (int64_t)m * p.ld + kg);
+      },
+      [&](int n, int kg) -> cplx {
+        if (n >= p.wp || kg >= ke) return cplx{0.0, 0.0};
+        return ld_elem<true>(W, (int64_t)n * p.nb + kg);
+      },
+      KFast());
   double* out = part + 2 * (int64_t)sp * 64 * 64;
   acc_foreach<true>(acc, [&](int m, int n, cplx v) { st_elem<true>(out, (int64_t)m * 64 + n, v); });
 }
@@ -580,7 +711,7 @@ __global__ void __launch_bounds__(NT) k_selinv_diag_final(Common c, PanelK p) {
   __shared__ double l_re[64][LDP];   // l[col][row] = Linv[row][col]
   __shared__ double l_im[64][LDP];
   __shared__ cplx dinv[64];
-  const int sh = blockIdx.y;
+  const int sh = p.sh0 + blockIdx.y;
   double* Ls = shift_base<true>(c, sh);
   const double* W = wbase(c, sh);
   const double* part = W + 2 * (int64_t)p.nb * p.wp;
@@ -743,6 +874,9 @@ PanelK panel_args(const Symbolic& S, const Panel& P) {
   k.nb = P.nb_rows;
   k.col0 = S.sfirst[P.J] + P.p0;
   k.split = split_count(P.nb_rows);
+  k.w = S.sfirst[P.J + 1] - S.sfirst[P.J];
+  k.c = S.ld[P.J] - k.w;
+  k.sh0 = 0;
   return k;
 }
 
@@ -765,6 +899,8 @@ Common make_common(const Symbolic& S, void* L, void* work) {
   c.info = (int64_t*)(w + WK_INFO);
   c.negc = (int64_t*)(w + WK_NEGC);
   c.pivtol = S.pivot_tol;
+  c.G = nullptr;
+  c.gstride = S.gather_per_shift / 8;
   return c;
 }
 
@@ -833,22 +969,37 @@ int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
   PXS_CHECK_LAUNCH();
   Common c = make_common(S, L, work);
   const double fm = CPLX ? 8.0 : 2.0;   // flops per multiply-add
-  for (const Panel& P : S.panels) {
+  const size_t np = S.panels.size();
+  for (size_t ip = 0; ip < np; ++ip) {
+    const Panel& P = S.panels[ip];
     PanelK k = panel_args(S, P);
+    if (k.p0 > 0) {
+      // left-looking: the panel's rows receive the earlier columns of its supernode
+      const int nrows = k.ld - k.p0;
+      ProfScope ps(KC_UPDATE, st, fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0);
+      hipLaunchKernelGGL(k_int_update<CPLX>, dim3((nrows + TM - 1) / TM, nshift), dim3(NT), 0, st, c, k);
+    }
     {
       ProfScope ps(KC_DIAG, st, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0);
       hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NT), 0, st, c, k);
     }
     if (k.nb > 0) {
       const int nt = (k.nb + TM - 1) / TM;
-      {
-        ProfScope ps(KC_TRSM, st, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
-        hipLaunchKernelGGL(k_trsm<CPLX>, dim3(nt, nshift), dim3(NT), 0, st, c, k);
-      }
-      {
-        ProfScope ps(KC_UPDATE, st, fm * nshift * (double)k.nb * (k.nb + 1) / 2.0 * k.wp);
-        hipLaunchKernelGGL(k_update<CPLX>, dim3(nt * (nt + 1) / 2, nshift), dim3(NT), 0, st, c, k);
-      }
+      ProfScope ps(KC_TRSM, st, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
+      hipLaunchKernelGGL(k_trsm<CPLX>, dim3(nt, nshift), dim3(NT), 0, st, c, k);
+    }
+    const bool last = (ip + 1 == np) || (S.panels[ip + 1].J != P.J);
+    const int32_t w = S.sfirst[P.J + 1] - S.sfirst[P.J];
+    const int32_t below = S.ld[P.J] - w;
+    if (last && below > 0) {
+      // right-looking: the whole supernode updates its ancestors once (K = w)
+      PanelK u = k;
+      u.p0 = 0;
+      u.wp = w;
+      u.nb = below;
+      const int nt = (below + TM - 1) / TM;
+      ProfScope ps(KC_UPDATE, st, fm * nshift * (double)below * (below + 1) / 2.0 * w);
+      hipLaunchKernelGGL(k_update<CPLX>, dim3(nt * (nt + 1) / 2, nshift), dim3(NT), 0, st, c, u);
     }
     PXS_CHECK_LAUNCH();
   }
@@ -860,25 +1011,45 @@ template int run_factor<false>(const Symbolic&, const double*, const double*, in
 
 int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st) {
   Common c = make_common(S, L, work);
-  for (auto it = S.panels.rbegin(); it != S.panels.rend(); ++it) {
-    PanelK k = panel_args(S, *it);
-    if (k.nb > 0) {
-      const int nt = (k.nb + TM - 1) / TM;
-      {
-        ProfScope ps(KC_LHAT, st, 8.0 * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
-        hipLaunchKernelGGL(k_lhat, dim3(nt, nshift), dim3(NT), 0, st, c, k);
+  c.G = (double*)((char*)work + S.work_fixed + (int64_t)nshift * S.work_per_shift);
+  const int chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
+  // supernodes from the root down; within a supernode, panels right to left
+  int ip = (int)S.panels.size() - 1;
+  while (ip >= 0) {
+    const int J = S.panels[ip].J;
+    int first = ip;
+    while (first > 0 && S.panels[first - 1].J == J) --first;
+    for (int sh0 = 0; sh0 < nshift; sh0 += chunk) {
+      const int ns = std::min(chunk, nshift - sh0);
+      PanelK g = panel_args(S, S.panels[ip]);
+      g.sh0 = sh0;
+      if (g.c > 0) {
+        const int nt = (g.c + TM - 1) / TM;
+        hipLaunchKernelGGL(k_gather_cc, dim3(nt * (nt + 1) / 2, ns), dim3(NT), 0, st, c, g);
       }
-      {
-        ProfScope ps(KC_SELINV_OFF, st, 8.0 * nshift * (double)k.nb * k.nb * k.wp);
-        hipLaunchKernelGGL(k_selinv_off, dim3(nt, nshift), dim3(NT), 0, st, c, k);
-      }
-      {
-        ProfScope ps(KC_SELINV_DIAG, st, 8.0 * nshift * (double)k.nb * k.wp * k.wp);
-        hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, nshift), dim3(NT), 0, st, c, k);
+      for (int q = ip; q >= first; --q) {
+        PanelK k = panel_args(S, S.panels[q]);
+        k.sh0 = sh0;
+        if (k.nb > 0) {
+          const int nt = (k.nb + TM - 1) / TM;
+          {
+            ProfScope ps(KC_LHAT, st, 8.0 * ns * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
+            hipLaunchKernelGGL(k_lhat, dim3(nt, ns), dim3(NT), 0, st, c, k);
+          }
+          {
+            ProfScope ps(KC_SELINV_OFF, st, 8.0 * ns * (double)k.nb * k.nb * k.wp);
+            hipLaunchKernelGGL(k_selinv_off, dim3(nt, ns), dim3(NT), 0, st, c, k);
+          }
+          {
+            ProfScope ps(KC_SELINV_DIAG, st, 8.0 * ns * (double)k.nb * k.wp * k.wp);
+            hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, ns), dim3(NT), 0, st, c, k);
+          }
+        }
+        hipLaunchKernelGGL(k_selinv_diag_final, dim3(1, ns), dim3(NT), 0, st, c, k);
+        PXS_CHECK_LAUNCH();
       }
     }
-    hipLaunchKernelGGL(k_selinv_diag_final, dim3(1, nshift), dim3(NT), 0, st, c, k);
-    PXS_CHECK_LAUNCH();
+    ip = first - 1;
   }
   return 0;
 }

@@ -63,11 +63,16 @@ struct Symbolic {
   int64_t o_colmap = 0, o_colseg = 0, o_entry_off = 0, o_relpos = 0, o_entry_diag = 0, o_diagoff = 0;
   std::vector<int64_t> diagoff;     // new column -> element offset of its diagonal entry
 
-  // Workspace layout per batch.
-  int64_t work_fixed = 0, work_per_shift = 0;
+  // Workspace layout per batch: work_fixed, then work_per_shift for every
+  // shift, then gather_per_shift (dense Z_CC of one supernode) for each shift
+  // of a SelInv chunk (selinv_chunk shifts, 0 = the whole batch).
+  int64_t work_fixed = 0, work_per_shift = 0, gather_per_shift = 0;
+  int32_t selinv_chunk = 0;
+  int32_t max_below_super = 0;      // max over supernodes of ld - w
 };
 
 struct AnalyzeOptions {
+  int selinv_chunk = 0;
   int ordering = 0;
   int leaf_cols = 128;
   int panel_width = 64;

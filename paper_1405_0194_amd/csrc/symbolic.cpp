@@ -533,6 +533,11 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
   S.work_per_shift = 16 * (S.max_below * pw + (int64_t)S.max_split * 64 * 64) + 16 * 8 + 256;
   S.work_per_shift = (S.work_per_shift + 255) / 256 * 256;
   S.work_fixed = 1 << 20;
+  S.max_below_super = 0;
+  for (int32_t J = 0; J < ns; ++J)
+    S.max_below_super = std::max(S.max_below_super, S.ld[J] - (S.sfirst[J + 1] - S.sfirst[J]));
+  S.gather_per_shift = (16 * (int64_t)S.max_below_super * S.max_below_super + 255) / 256 * 256;
+  S.selinv_chunk = std::max(0, opt.selinv_chunk);
   return 0;
 }
 
