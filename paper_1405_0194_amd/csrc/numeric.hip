@@ -75,58 +75,76 @@ __device__ __forceinline__ void st_elem(double* base, int64_t e, cplx v) {
 }
 
 // --------------------------------------------------------------------------
-// MFMA tile engine: a 256-thread workgroup accumulates a 64 x 64 tile
-// P[m][n] = sum_k A[m][k] B[k][n].  Wave w owns rows 32*(w>>1) .. +32 and
-// columns 32*(w&1) .. +32 as 2 x 2 blocks of 16 x 16.  Operands are staged
-// in LDS as As[k][m], Bs[k][n] (real and imaginary parts split).
+// MFMA tile engine: a 256-thread workgroup accumulates a 64 x NTILE tile
+// P[m][n] = sum_k A[m][k] B[k][n] (NTILE = 64 or 128).  The 4 waves are laid
+// out WM x WN over the tile, each owning BM x BN blocks of 16 x 16.
+// Operands are staged in LDS as As[k][m], Bs[k][n] (real and imaginary
+// parts split, rows padded by one double).
 // v_mfma_f64_16x16x4f64 lane layout (lane l, 0..63):
 //   A operand: A[l % 16][l / 16];  B operand: B[l / 16][l % 16];
 //   result register r: D[l / 16 + 4 r][l % 16].
+// A complex block product is four real MFMAs: re += ar br - ai bi,
+// im += ar bi + ai br.
 // --------------------------------------------------------------------------
-template <bool CPLX>
+template <int NTILE>
+struct Geo {
+  static constexpr int WN = NTILE / 32;        // waves along n
+  static constexpr int WM = 4 / WN;            // waves along m
+  static constexpr int BM = 64 / WM / 16;      // 16-blocks per wave along m
+  static constexpr int BN = 2;                 // 16-blocks per wave along n
+  static constexpr int XA = 64 * KC / NT;      // A transfers per thread and chunk
+  static constexpr int XB = NTILE * KC / NT;   // B transfers per thread and chunk
+};
+
+template <bool CPLX, int NTILE>
 struct Acc {
-  dbl4 re[2][2];
-  dbl4 im[2][2];
+  static constexpr int BM = Geo<NTILE>::BM, BN = Geo<NTILE>::BN;
+  dbl4 re[BM][BN];
+  dbl4 im[CPLX ? BM : 1][CPLX ? BN : 1];
   __device__ void zero() {
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b) {
         re[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
         if (CPLX) im[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
       }
   }
 };
 
-template <bool CPLX>
+template <bool CPLX, int NTILE>
 struct Stage {
   double a_re[KC][LDP];
   double a_im[CPLX ? KC : 1][LDP];
-  double b_re[KC][LDP];
-  double b_im[CPLX ? KC : 1][LDP];
+  double b_re[KC][NTILE + 1];
+  double b_im[CPLX ? KC : 1][NTILE + 1];
 };
 
-template <bool CPLX>
-__device__ __forceinline__ void mfma_chunk(Acc<CPLX>& acc, const Stage<CPLX>& s) {
+template <bool CPLX, int NTILE>
+__device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CPLX, NTILE>& s) {
+  using G = Geo<NTILE>;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int wm = (w / G::WN) * (G::BM * 16), wn = (w % G::WN) * 32;
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int ks = 0; ks < KC / 4; ++ks) {
     const int k = ks * 4 + lk;
-    double ar[2], ai[2], br[2], bi[2];
+    double ar[G::BM], ai[G::BM], br[G::BN], bi[G::BN];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < G::BM; ++t) {
       ar[t] = s.a_re[k][wm + t * 16 + li];
-      br[t] = s.b_re[k][wn + t * 16 + li];
-      if (CPLX) {
-        ai[t] = s.a_im[k][wm + t * 16 + li];
-        bi[t] = s.b_im[k][wn + t * 16 + li];
-      }
+      if (CPLX) ai[t] = s.a_im[k][wm + t * 16 + li];
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int t = 0; t < G::BN; ++t) {
+      br[t] = s.b_re[k][wn + t * 16 + li];
+      if (CPLX) bi[t] = s.b_im[k][wn + t * 16 + li];
+    }
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+    for (int a = 0; a < G::BM; ++a)
+#pragma unroll
+      for (int b = 0; b < G::BN; ++b) {
         acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc.re[a][b], 0, 0, 0);
         if (CPLX) {
           acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[a], bi[b], acc.re[a][b], 0, 0, 0);
@@ -138,15 +156,16 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX>& acc, const Stage<CPLX>& s)
 }
 
 // Visits every accumulator element as (m, n, value).
-template <bool CPLX, class F>
-__device__ __forceinline__ void acc_foreach(const Acc<CPLX>& acc, F f) {
+template <bool CPLX, int NTILE, class F>
+__device__ __forceinline__ void acc_foreach(const Acc<CPLX, NTILE>& acc, F f) {
+  using G = Geo<NTILE>;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int wm = (w / G::WN) * (G::BM * 16), wn = (w % G::WN) * 32;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < G::BM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < G::BN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = wm + a * 16 + (lane >> 4) + 4 * r;
@@ -156,82 +175,101 @@ __device__ __forceinline__ void acc_foreach(const Acc<CPLX>& acc, F f) {
       }
 }
 
-// Staging of one k-chunk.  slot(j) gives the (idx, k) pair that thread t
-// moves in its j-th of four transfers: FAST_K = false puts consecutive
-// threads on consecutive idx (memory contiguous along idx), FAST_K = true on
-// consecutive k.  fetch() reads global memory into registers, commit()
-// writes the registers to LDS, so the next chunk's loads can be in flight
-// while the current chunk runs on the matrix cores.
-template <bool FAST_K>
+// Staging of one k-chunk of an operand with ROWS rows (64 or NTILE).
+// slot(j) gives the (row, k) pair thread t moves in its j-th transfer:
+// FAST_K = false puts consecutive threads on consecutive rows (memory
+// contiguous along the rows), FAST_K = true on consecutive k.  fetch() reads
+// global memory into registers and commit() writes them to LDS, so the next
+// chunk's loads are in flight while the current chunk runs on the matrix
+// cores.
+template <int ROWS, bool FAST_K>
 __device__ __forceinline__ void slot(int j, int& ii, int& kk) {
   const int t = threadIdx.x;
   if (!FAST_K) {
-    ii = t & 63;
-    kk = (t >> 6) + 4 * j;
+    ii = t % ROWS;
+    kk = t / ROWS + (NT / ROWS) * j;
   } else {
-    kk = t & 15;
-    ii = (t >> 4) + 16 * j;
+    kk = t % KC;
+    ii = t / KC + (NT / KC) * j;
   }
 }
 
-template <bool FAST_K, class G>
-__device__ __forceinline__ void fetch(cplx (&v)[4], int k0, G get) {
+template <int ROWS, int X, bool FAST_K, class Gt>
+__device__ __forceinline__ void fetch(cplx (&v)[X], int k0, Gt get) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < X; ++j) {
     int ii, kk;
-    slot<FAST_K>(j, ii, kk);
+    slot<ROWS, FAST_K>(j, ii, kk);
     v[j] = get(ii, k0 + kk);
   }
 }
 
-template <bool CPLX, bool FAST_K>
-__device__ __forceinline__ void commit(double (*re)[LDP], double (*im)[LDP], const cplx (&v)[4]) {
+template <bool CPLX, int ROWS, int X, bool FAST_K>
+__device__ __forceinline__ void commit(double* re, double* im, const cplx (&v)[X]) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < X; ++j) {
     int ii, kk;
-    slot<FAST_K>(j, ii, kk);
-    re[kk][ii] = v[j].re;
-    if (CPLX) im[kk][ii] = v[j].im;
+    slot<ROWS, FAST_K>(j, ii, kk);
+    re[kk * (ROWS + 1) + ii] = v[j].re;
+    if (CPLX) im[kk * (ROWS + 1) + ii] = v[j].im;
   }
 }
 
-template <class G>
-__device__ __forceinline__ void fetch_rt(cplx (&v)[4], int k0, G get, bool fast) {
-  if (fast) fetch<true>(v, k0, get);
-  else fetch<false>(v, k0, get);
+template <int ROWS, int X, class Gt>
+__device__ __forceinline__ void fetch_rt(cplx (&v)[X], int k0, Gt get, bool fast) {
+  if (fast) fetch<ROWS, X, true>(v, k0, get);
+  else fetch<ROWS, X, false>(v, k0, get);
 }
-template <bool CPLX>
-__device__ __forceinline__ void commit_rt(double (*re)[LDP], double (*im)[LDP], const cplx (&v)[4], bool fast) {
-  if (fast) commit<CPLX, true>(re, im, v);
-  else commit<CPLX, false>(re, im, v);
+template <bool CPLX, int ROWS, int X>
+__device__ __forceinline__ void commit_rt(double* re, double* im, const cplx (&v)[X], bool fast) {
+  if (fast) commit<CPLX, ROWS, X, true>(re, im, v);
+  else commit<CPLX, ROWS, X, false>(re, im, v);
 }
 
 // Software-pipelined K loop over [kb, ke): P += A[:, k] B[k, :].  ga(m, k)
 // and gb(n, k) return the operands (zero outside the matrices); bfast(k0)
 // picks the B staging order per chunk (uniform across the workgroup).
-template <bool CPLX, bool AFAST, class GA, class GB, class BF>
-__device__ __forceinline__ void gemm_pipe(Acc<CPLX>& acc, Stage<CPLX>& s, int kb, int ke, GA ga, GB gb,
-                                          BF bfast) {
-  cplx ra[4], rb[4];
+template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF>
+__device__ __forceinline__ void gemm_pipe(Acc<CPLX, NTILE>& acc, Stage<CPLX, NTILE>& s, int kb, int ke,
+                                          GA ga, GB gb, BF bfast) {
+  using G = Geo<NTILE>;
+  cplx ra[G::XA], rb[G::XB];
   bool fb = false;
   if (kb < ke) {
     fb = bfast(kb);
-    fetch<AFAST>(ra, kb, ga);
-    fetch_rt(rb, kb, gb, fb);
+    fetch<64, G::XA, AFAST>(ra, kb, ga);
+    fetch_rt<NTILE, G::XB>(rb, kb, gb, fb);
   }
   for (int k0 = kb; k0 < ke; k0 += KC) {
     __syncthreads();
-    commit<CPLX, AFAST>(s.a_re, s.a_im, ra);
-    commit_rt<CPLX>(s.b_re, s.b_im, rb, fb);
+    commit<CPLX, 64, G::XA, AFAST>(&s.a_re[0][0], &s.a_im[0][0], ra);
+    commit_rt<CPLX, NTILE, G::XB>(&s.b_re[0][0], &s.b_im[0][0], rb, fb);
     __syncthreads();
     const int k1 = k0 + KC;
     if (k1 < ke) {
       fb = bfast(k1);
-      fetch<AFAST>(ra, k1, ga);
-      fetch_rt(rb, k1, gb, fb);
+      fetch<64, G::XA, AFAST>(ra, k1, ga);
+      fetch_rt<NTILE, G::XB>(rb, k1, gb, fb);
     }
-    mfma_chunk<CPLX>(acc, s);
+    mfma_chunk<CPLX, NTILE>(acc, s);
   }
+}
+
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
+// XCDs in linear-id order; this bijection gives each XCD a contiguous range
+// of logical ids, so the tiles of one shift (which share the A operand) run
+// on the same XCD and share its L2.  Returns the logical (x, y) of the
+// caller in a grid of nx x ny.
+constexpr int NXCD = 8;
+__device__ __forceinline__ void xcd_remap(int& x, int& y) {
+  const int nx = gridDim.x, ny = gridDim.y;
+  const int total = nx * ny;
+  const int b = blockIdx.x + nx * blockIdx.y;
+  const int xcd = b % NXCD, idx = b / NXCD;
+  const int q = total / NXCD, r = total % NXCD;
+  const int logical = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+  x = logical % nx;
+  y = logical / nx;
 }
 
 struct RowsFast {
@@ -429,22 +467,26 @@ __global__ void __launch_bounds__(NT) k_diag(Common c, PanelK p) {
 }
 
 // L_Bp = A_Bp L_pp^{-T} D^{-1}: P[c][i] = sum_k Linv[c][k] A[i][k], then / d_c.
+constexpr int TN = 128;   // rows per workgroup of the panel products
+
 template <bool CPLX>
-__global__ void __launch_bounds__(NT) k_trsm(Common c, PanelK p) {
-  __shared__ Stage<CPLX> s;
+__global__ void __launch_bounds__(NT, 2) k_trsm(Common c, PanelK p) {
+  __shared__ Stage<CPLX, TN> s;
   __shared__ cplx dinv[64];
-  const int sh = blockIdx.y;
+  int bx, by;
+  xcd_remap(bx, by);
+  const int sh = by;
   double* Ls = shift_base<CPLX>(c, sh);
-  const int i0 = blockIdx.x * TM;
+  const int i0 = bx * TN;
   const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;   // (p0, p0)
   const int64_t rbase = dbase + p.wp;                          // first row below
   if (threadIdx.x < p.wp) {
     const cplx d = ld_elem<CPLX>(Ls, dbase + (int64_t)threadIdx.x * p.ld + threadIdx.x);
     dinv[threadIdx.x] = CPLX ? cinv(d) : cplx{1.0 / d.re, 0.0};
   }
-  Acc<CPLX> acc;
+  Acc<CPLX, TN> acc;
   acc.zero();
-  gemm_pipe<CPLX, false>(
+  gemm_pipe<CPLX, TN, false>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[c][k]: column k of the diagonal block
         if (m >= p.wp || kg >= p.wp || m < kg) return cplx{0.0, 0.0};
@@ -457,7 +499,7 @@ __global__ void __launch_bounds__(NT) k_trsm(Common c, PanelK p) {
         return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
       },
       RowsFast());
-  acc_foreach<CPLX>(acc, [&](int m, int n, cplx v) {
+  acc_foreach<CPLX, TN>(acc, [&](int m, int n, cplx v) {
     const int ig = i0 + n;
     if (m < p.wp && ig < p.nb) st_elem<CPLX>(Ls, rbase + (int64_t)m * p.ld + ig, cmul(v, dinv[m]));
   });
@@ -467,16 +509,18 @@ __global__ void __launch_bounds__(NT) k_trsm(Common c, PanelK p) {
 // supernode: A[r][c] -= sum_{k < p0} L[r][k] d_k L[c][k] for rows r >= p0 of
 // the row list and the panel's columns c.  P[c][r] = sum_k (d_k L[c][k]) L[r][k].
 template <bool CPLX>
-__global__ void __launch_bounds__(NT) k_int_update(Common c, PanelK p) {
-  __shared__ Stage<CPLX> s;
-  const int sh = blockIdx.y;
+__global__ void __launch_bounds__(NT, 2) k_int_update(Common c, PanelK p) {
+  __shared__ Stage<CPLX, TN> s;
+  int bx, by;
+  xcd_remap(bx, by);
+  const int sh = by;
   double* Ls = shift_base<CPLX>(c, sh);
-  const int r0 = blockIdx.x * TM;            // rows p0 + r0 .. of the row list
+  const int r0 = bx * TN;            // rows p0 + r0 .. of the row list
   const int nrows = p.ld - p.p0;
   const int64_t cbase = p.off + p.p0;        // element (row p0, column 0)
-  Acc<CPLX> acc;
+  Acc<CPLX, TN> acc;
   acc.zero();
-  gemm_pipe<CPLX, false>(
+  gemm_pipe<CPLX, TN, false>(
       acc, s, 0, p.p0,
       [&](int m, int kg) -> cplx {   // d_k L[p0 + c][k]
         if (m >= p.wp || kg >= p.p0) return cplx{0.0, 0.0};
@@ -489,7 +533,7 @@ __global__ void __launch_bounds__(NT) k_int_update(Common c, PanelK p) {
         return ld_elem<CPLX>(Ls, cbase + (int64_t)kg * p.ld + rg);
       },
       RowsFast());
-  acc_foreach<CPLX>(acc, [&](int m, int n, cplx v) {
+  acc_foreach<CPLX, TN>(acc, [&](int m, int n, cplx v) {
     const int rg = r0 + n;
     if (m < p.wp && rg < nrows && rg >= m) {
       const int64_t e = cbase + (int64_t)(p.p0 + m) * p.ld + rg;
@@ -516,19 +560,24 @@ __device__ __forceinline__ void tri_index(int b, int& ti, int& tj) {
 // with K = all of its columns (p0 = 0, wp = w_J, B = the rows below it).
 // P[j][i] = sum_k (d_k L[j][k]) L[i][k].
 template <bool CPLX>
-__global__ void __launch_bounds__(NT) k_update(Common c, PanelK p) {
-  __shared__ Stage<CPLX> s;
-  const int sh = blockIdx.y;
+__global__ void __launch_bounds__(NT, 2) k_update(Common c, PanelK p) {
+  __shared__ Stage<CPLX, TN> s;
+  int bx, by;
+  xcd_remap(bx, by);
+  const int sh = by;
   double* Ls = shift_base<CPLX>(c, sh);
-  int ti, tj;
-  tri_index(blockIdx.x, ti, tj);
-  const int i0 = ti * TM, j0 = tj * TM;
+  // tiles: 64 columns j (m) by 128 rows i (n); only tiles that reach the
+  // lower triangle (some i >= some j) do work
+  const int nti = (p.nb + TN - 1) / TN;
+  const int tj = bx / nti, ti = bx % nti;
+  const int i0 = ti * TN, j0 = tj * TM;
+  if (i0 + TN - 1 < j0) return;
   const int base = p.p0 + p.wp;   // row-list position of the first row below
   const int64_t rbase = p.off + base;   // element (row base, column 0)
   const int kb = p.p0, ke = p.p0 + p.wp;
-  Acc<CPLX> acc;
+  Acc<CPLX, TN> acc;
   acc.zero();
-  gemm_pipe<CPLX, false>(
+  gemm_pipe<CPLX, TN, false>(
       acc, s, kb, ke,
       [&](int m, int kg) -> cplx {
         const int jg = j0 + m;
@@ -544,7 +593,7 @@ __global__ void __launch_bounds__(NT) k_update(Common c, PanelK p) {
       RowsFast());
   const int64_t* cmap = c.colmap + p.cm;
   const int64_t* cseg = c.colseg + p.cm;
-  acc_foreach<CPLX>(acc, [&](int m, int n, cplx v) {
+  acc_foreach<CPLX, TN>(acc, [&](int m, int n, cplx v) {
     const int jg = j0 + m, ig = i0 + n;
     if (jg < p.nb && ig < p.nb && ig >= jg) {
       const int qj = base + jg, qi = base + ig;
@@ -565,17 +614,19 @@ __device__ __forceinline__ double* wbase(const Common& c, int sh) {
 }
 
 // W = L_Bp Linv: P[c][i] = sum_k Linv[k][c] L[i][k]; W stored W[c * nb + i].
-__global__ void __launch_bounds__(NT) k_lhat(Common c, PanelK p) {
-  __shared__ Stage<true> s;
-  const int sh = p.sh0 + blockIdx.y;
+__global__ void __launch_bounds__(NT, 2) k_lhat(Common c, PanelK p) {
+  __shared__ Stage<true, TN> s;
+  int bx, by;
+  xcd_remap(bx, by);
+  const int sh = p.sh0 + by;
   double* Ls = shift_base<true>(c, sh);
   double* W = wbase(c, sh);
-  const int i0 = blockIdx.x * TM;
+  const int i0 = bx * TN;
   const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;
   const int64_t rbase = dbase + p.wp;
-  Acc<true> acc;
+  Acc<true, TN> acc;
   acc.zero();
-  gemm_pipe<true, true>(
+  gemm_pipe<true, TN, true>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[k][c]: column c of the diagonal block, rows k
         if (m >= p.wp || kg >= p.wp || kg < m) return cplx{0.0, 0.0};
@@ -588,7 +639,7 @@ __global__ void __launch_bounds__(NT) k_lhat(Common c, PanelK p) {
         return ld_elem<true>(Ls, rbase + (int64_t)kg * p.ld + ig);
       },
       RowsFast());
-  acc_foreach<true>(acc, [&](int m, int n, cplx v) {
+  acc_foreach<true, TN>(acc, [&](int m, int n, cplx v) {
     const int ig = i0 + n;
     if (m < p.wp && ig < p.nb) st_elem<true>(W, (int64_t)m * p.nb + ig, v);
   });
@@ -598,17 +649,19 @@ __global__ void __launch_bounds__(NT) k_lhat(Common c, PanelK p) {
 // part inside the supernode's own columns is read from the supernode's
 // storage (column min(i, k), row max(i, k)), the part in the rows below it
 // from the dense copy G of Z_CC made by k_gather_cc.
-__global__ void __launch_bounds__(NT) k_selinv_off(Common c, PanelK p) {
-  __shared__ Stage<true> s;
-  const int sh = p.sh0 + blockIdx.y;
+__global__ void __launch_bounds__(NT, 2) k_selinv_off(Common c, PanelK p) {
+  __shared__ Stage<true, TN> s;
+  int bx, by;
+  xcd_remap(bx, by);
+  const int sh = p.sh0 + by;
   double* Ls = shift_base<true>(c, sh);
   const double* W = wbase(c, sh);
-  const double* G = c.G + c.gstride * blockIdx.y;
-  const int i0 = blockIdx.x * TM;
+  const double* G = c.G + c.gstride * by;
+  const int i0 = bx * TN;
   const int base = p.p0 + p.wp;
-  Acc<true> acc;
+  Acc<true, TN> acc;
   acc.zero();
-  gemm_pipe<true, true>(
+  gemm_pipe<true, TN, true>(
       acc, s, 0, p.nb,
       [&](int m, int kg) -> cplx {
         if (m >= p.wp || kg >= p.nb) return cplx{0.0, 0.0};
@@ -629,7 +682,7 @@ __global__ void __launch_bounds__(NT) k_selinv_off(Common c, PanelK p) {
         return !rows;
       });
   const int64_t rbase = p.off + (int64_t)p.p0 * p.ld + base;
-  acc_foreach<true>(acc, [&](int m, int n, cplx v) {
+  acc_foreach<true, TN>(acc, [&](int m, int n, cplx v) {
     const int ig = i0 + n;
     if (m < p.wp && ig < p.nb) st_elem<true>(Ls, rbase + (int64_t)m * p.ld + ig, cplx{-v.re, -v.im});
   });
@@ -679,19 +732,21 @@ __global__ void __launch_bounds__(NT) k_gather_cc(Common c, PanelK p) {
 }
 
 // Partial W^T Z_Bp over k in [split * 512, ...): P[c][r] = sum_k Z[k][c] W[k][r].
-__global__ void __launch_bounds__(NT) k_selinv_diag_partial(Common c, PanelK p) {
-  __shared__ Stage<true> s;
-  const int sh = p.sh0 + blockIdx.y;
-  const int sp = blockIdx.x;
+__global__ void __launch_bounds__(NT, 2) k_selinv_diag_partial(Common c, PanelK p) {
+  __shared__ Stage<true, TM> s;
+  int bx, by;
+  xcd_remap(bx, by);
+  const int sh = p.sh0 + by;
+  const int sp = bx;
   double* Ls = shift_base<true>(c, sh);
   double* W = wbase(c, sh);
   double* part = W + 2 * (int64_t)p.nb * p.wp;   // after W: split x 64 x 64 complex
   const int base = p.p0 + p.wp;
   const int64_t rbase = p.off + (int64_t)p.p0 * p.ld + base;
   const int kb = sp * 512, ke = min(p.nb, kb + 512);
-  Acc<true> acc;
+  Acc<true, TM> acc;
   acc.zero();
-  gemm_pipe<true, true>(
+  gemm_pipe<true, TM, true>(
       acc, s, kb, ke,
       [&](int m, int kg) -> cplx {
         if (m >= p.wp || kg >= ke) return cplx{0.0, 0.0};
@@ -703,7 +758,7 @@ __global__ void __launch_bounds__(NT) k_selinv_diag_partial(Common c, PanelK p) 
       },
       KFast());
   double* out = part + 2 * (int64_t)sp * 64 * 64;
-  acc_foreach<true>(acc, [&](int m, int n, cplx v) { st_elem<true>(out, (int64_t)m * 64 + n, v); });
+  acc_foreach<true, TM>(acc, [&](int m, int n, cplx v) { st_elem<true>(out, (int64_t)m * 64 + n, v); });
 }
 
 // Z_pp = Linv^T D^{-1} Linv - sum of the partials, written over the diagonal block.
@@ -977,14 +1032,14 @@ int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
       // left-looking: the panel's rows receive the earlier columns of its supernode
       const int nrows = k.ld - k.p0;
       ProfScope ps(KC_UPDATE, st, fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0);
-      hipLaunchKernelGGL(k_int_update<CPLX>, dim3((nrows + TM - 1) / TM, nshift), dim3(NT), 0, st, c, k);
+      hipLaunchKernelGGL(k_int_update<CPLX>, dim3((nrows + TN - 1) / TN, nshift), dim3(NT), 0, st, c, k);
     }
     {
       ProfScope ps(KC_DIAG, st, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0);
       hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NT), 0, st, c, k);
     }
     if (k.nb > 0) {
-      const int nt = (k.nb + TM - 1) / TM;
+      const int nt = (k.nb + TN - 1) / TN;
       ProfScope ps(KC_TRSM, st, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
       hipLaunchKernelGGL(k_trsm<CPLX>, dim3(nt, nshift), dim3(NT), 0, st, c, k);
     }
@@ -997,9 +1052,9 @@ int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
       u.p0 = 0;
       u.wp = w;
       u.nb = below;
-      const int nt = (below + TM - 1) / TM;
+      const int ntj = (below + TM - 1) / TM, nti = (below + TN - 1) / TN;
       ProfScope ps(KC_UPDATE, st, fm * nshift * (double)below * (below + 1) / 2.0 * w);
-      hipLaunchKernelGGL(k_update<CPLX>, dim3(nt * (nt + 1) / 2, nshift), dim3(NT), 0, st, c, u);
+      hipLaunchKernelGGL(k_update<CPLX>, dim3(ntj * nti, nshift), dim3(NT), 0, st, c, u);
     }
     PXS_CHECK_LAUNCH();
   }
@@ -1031,7 +1086,7 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
         PanelK k = panel_args(S, S.panels[q]);
         k.sh0 = sh0;
         if (k.nb > 0) {
-          const int nt = (k.nb + TM - 1) / TM;
+          const int nt = (k.nb + TN - 1) / TN;
           {
             ProfScope ps(KC_LHAT, st, 8.0 * ns * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
             hipLaunchKernelGGL(k_lhat, dim3(nt, ns), dim3(NT), 0, st, c, k);
