@@ -28,6 +28,14 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
+MULTI = {
+    "batch": "64 uneven systems (chain / honeycomb / cubic, kind = s mod 3), N log-uniform in "
+             "[500, 8000], 40-80 poles each, graph-captured plans over 4 HIP streams, 250 GiB budget",
+    "serve": "Poisson request stream: sizes Zipf(1.2) over k*1000 basis functions, chain / honeycomb / "
+             "cubic, 40 poles, 30% SCF-style repeats of a resident pattern, 16-shift inertia counts on "
+             "new patterns, 250 GiB admission budget, 4 streams",
+}
+
 WORKLOADS = {
     "honeycomb": dict(cfg=1, desc="periodic honeycomb 32x32 cells x 2 atoms x 13 orbitals, "
                       "cutoff 3 NN distances, N=26624, 60 poles, one batch"),
@@ -91,14 +99,97 @@ def cpu_baseline(full_n, seconds_target=15.0):
                        f"scaled by (N_sample/N)^3 to N={full_n}")}
 
 
+def per_pole_sample(a, H, S, beta, dE, mu, P, nsample):
+    """The plain per-pole loop (same kernels, one shift per factorization,
+    no batching, no graphs) on the first nsample shifts: seconds per shift."""
+    import torch
+    from paper_1405_0194_amd import batch
+    from paper_1405_0194_amd import binding as B
+    sh, wt = B.poles(beta, dE, mu, P, 2)
+    batch.per_pole_loop(a, H, S, sh[:1], wt[:, :1])      # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    batch.per_pole_loop(a, H, S, sh[:nsample], wt[:, :nsample])
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) / nsample
+
+
+def run_batch(args):
+    import torch
+    from paper_1405_0194_amd import lattice
+    from paper_1405_0194_amd.batch import BatchRunner, Job
+    t = time.perf_counter()
+    items = lattice.batch_systems()
+    jobs = [Job(system=s, poles=P, mu=0.0) for s, P in items]
+    print(f"# batch: {len(jobs)} systems generated in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
+    br = BatchRunner(jobs, budget_bytes=250 * 2**30, nstreams=4)
+    for i in range(args.warmup):
+        print(f"# warmup {i}: {br.run():.2f}s", file=sys.stderr, flush=True)
+    times = []
+    for i in range(args.steps):
+        times.append(br.run())
+        print(f"# step {i}: {times[-1]:.2f}s", file=sys.stderr, flush=True)
+    elapsed = sum(times)
+    solves = br.total_solves() * args.steps
+    flops = br.total_flops() * args.steps
+    seq = BatchRunner(jobs, budget_bytes=250 * 2**30, nstreams=1)
+    t1 = seq.run()
+    print(f"# one stream: {t1:.2f}s", file=sys.stderr, flush=True)
+    res = dict(value=round(solves / elapsed, 4), ms_per_step=round(1e3 * elapsed / args.steps, 3),
+               path_tflops=round(flops / elapsed / 1e12, 3),
+               fp64_mfma_pct=round(100.0 * flops / elapsed / 1e12 / PEAK_FP64_TFLOPS, 2),
+               latency_s={"p50": round(float(np.percentile(times, 50)), 4),
+                          "p99": round(float(np.percentile(times, 99)), 4)},
+               one_stream_pole_solves_per_s=round(br.total_solves() / t1, 4),
+               config={"workload": MULTI["batch"], "systems": len(jobs), "pole_solves_per_step": br.total_solves(),
+                       "tflop_per_step": round(br.total_flops() / 1e12, 2)})
+    return res
+
+
+def run_serve(args):
+    import torch
+    from paper_1405_0194_amd import lattice
+    from paper_1405_0194_amd.serve import Request, Server, poisson_arrivals
+    t = time.perf_counter()
+    raw = lattice.serving_requests(args.requests, kmax=args.kmax)
+    print(f"# serve: {len(raw)} requests generated in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
+
+    def make():
+        return [Request(system=r["system"], mu=r["mu"], poles=40, eps=r["eps"]) for r in raw]
+    srv = Server(budget_bytes=250 * 2**30, nstreams=4)
+    sat = srv.run(make(), realtime=False)         # saturated: everything queued at t = 0
+    print(f"# saturated: {sat}", file=sys.stderr, flush=True)
+    lam = sat["req_per_s"]
+    runs = {}
+    for f in (0.5, 0.8):
+        reqs = make()
+        for q, ta in zip(reqs, poisson_arrivals(len(reqs), f * lam, seed=int(f * 10))):
+            q.arrival = float(ta)
+        runs[f] = srv.run(reqs, realtime=True)
+        print(f"# load {f}: {runs[f]}", file=sys.stderr, flush=True)
+    r8 = runs[0.8]
+    res = dict(value=round(r8["pole_solves_per_s"], 4), ms_per_step=round(1e3 * r8["makespan_s"], 3),
+               latency_s={"p50": round(r8["p50_s"], 4), "p99": round(r8["p99_s"], 4)},
+               saturated={k: (round(v, 4) if isinstance(v, float) else v) for k, v in sat.items()},
+               load_0_5={k: (round(v, 4) if isinstance(v, float) else v) for k, v in runs[0.5].items()},
+               load_0_8={k: (round(v, 4) if isinstance(v, float) else v) for k, v in r8.items()},
+               config={"workload": MULTI["serve"], "requests": len(raw), "kmax": args.kmax,
+                       "rate_req_per_s_at_0_8": round(0.8 * lam, 4)})
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="honeycomb", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="honeycomb", choices=sorted(WORKLOADS) + sorted(MULTI))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernel", default="selinv_off")
+    ap.add_argument("--compare-perpole", type=int, default=0,
+                    help="also time the plain per-pole loop on this many shifts")
+    ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
+    ap.add_argument("--kmax", type=int, default=16, help="serve: largest size class (k * 1000)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -110,6 +201,21 @@ def main():
     import torch
     from paper_1405_0194_amd import binding as B
     from paper_1405_0194_amd import lattice
+    globals()["np"] = np
+
+    if args.workload in MULTI:
+        torch.cuda.set_device(0)
+        res = run_batch(args) if args.workload == "batch" else run_serve(args)
+        steps = args.steps if args.workload == "batch" else 1
+        warm = args.warmup if args.workload == "batch" else 0
+        line = {"metric": "pole-solves/sec (LDL^T+SelInv), FP64 MFMA %, p50/p99 request latency",
+                "value": res.pop("value"), "unit": "pole-solves/s", "n_gpus": 1, "steps": steps,
+                "warmup": warm, "ms_per_step": res.pop("ms_per_step"), "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+                "config": res.pop("config")}
+        line.update(res)
+        print(json.dumps(line), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     cfg = wl["cfg"]
@@ -211,6 +317,11 @@ def main():
         gbs = (kwork / max(klaunch, 1)) / (avg_ms / 1e3) / 1e9 if klaunch else 0.0
         res["roofline"].update({"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                                 "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)})
+    if args.compare_perpole:
+        del f
+        sec = per_pole_sample(a, H, S, beta, dE, mu, P, args.compare_perpole)
+        res["per_pole_loop"] = {"pole_solves_per_s": round(1.0 / sec, 4), "shifts_timed": args.compare_perpole,
+                                "speedup_of_batched": round(value * sec, 3)}
     if not args.no_cpu_baseline:
         del L, W
         torch.cuda.empty_cache()

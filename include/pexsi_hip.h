@@ -196,6 +196,35 @@ pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double
                               int64_t* info, pxs_c64* shifts, pxs_c64* weights,
                               void* stream);
 
+/* ---------------------------------------------------------------------- */
+/* Graph-captured density matrix (the batched execution of all shifts as one
+ * replayable HIP graph).  pxs_plan_create captures assembly, LDL^T, selected
+ * inversion and the pole sums of nsets weight sets for nshift shifts, bound
+ * to these buffers (same conventions as pxs_factor / pxs_pole_sum; out is
+ * device nsets * nnz_lower).  Shifts and weights are read from the workspace
+ * when the graph runs, so one plan serves every pole table of the same size
+ * and new H/S values on the same pattern (SCF-style repeats).  The capture
+ * uses a private stream; creating a plan runs nothing.
+ * pxs_plan_run uploads shifts[nshift] and weights[nsets * nshift] (host) on
+ * `stream` and replays the graph there; traces (host, 2 * nsets) and info
+ * (host, nshift) are optional and synchronise the stream.  Calls on one plan
+ * must not overlap (they share the buffers).
+ * flags: 0, or PXS_PLAN_ACCUMULATE: the pole sums are added to `out`
+ * instead of overwriting it, so a system too large for one batch can run its
+ * poles in chunks into one output (the traces then cover the last chunk). */
+typedef struct pxs_plan_s* pxs_plan;
+enum { PXS_PLAN_ACCUMULATE = 1 };
+pxs_status pxs_plan_create(pxs_symbolic sym, const double* Hval, const double* Sval,
+                           int32_t nshift, int32_t nsets, void* Lbuf, void* work, double* out,
+                           int32_t flags, pxs_plan* plan);
+pxs_status pxs_plan_run(pxs_plan plan, const pxs_c64* shifts, const pxs_c64* weights,
+                        double* traces, int64_t* info, void* stream);
+/* Traces (host, 2 * nsets, nullable) and info (host, nshift, nullable) of
+ * the last run of the plan, after synchronising `stream` (the stream the run
+ * was enqueued on, or one ordered after it). */
+pxs_status pxs_plan_results(pxs_plan plan, double* traces, int64_t* info, void* stream);
+void pxs_plan_free(pxs_plan plan);
+
 /* Kernel timing for benchmarks: while a profile is open, every launch of the
  * selected kernel class is bracketed by HIP events on its launch stream.
  * kernel: 1 factor update, 2 SelInv off-diagonal product, 3 panel TRSM,

@@ -1,0 +1,144 @@
+"""Batched execution of many uneven systems on one GPU.
+
+Every system keeps its own symbolic analysis and device maps; all of its
+shifts run as one graph-captured plan (pxs_plan_create / pxs_plan_run), i.e.
+as the batch dimension of every launch.  Systems are admitted in decreasing
+order of work while their device footprint fits the memory budget, and are
+spread over several HIP streams so that small systems overlap with large
+ones (the paper's pole-level and system-level independence, Sec. II.B, taken
+to one device).  Host-side orchestration only: every numeric step runs in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+from . import binding as B
+from .lattice import BETA_300K
+
+
+@dataclasses.dataclass
+class Job:
+    system: object
+    poles: int
+    mu: float = 0.0
+    beta: float = BETA_300K
+    nsets: int = 2
+    analysis: object = None
+    footprint: int = 0          # device bytes while running (factor + workspace + output)
+    flops: float = 0.0
+    # results
+    out: object = None          # device tensor (nsets, nnz) when keep_outputs
+    traces: object = None
+    info: object = None
+    t_submit: float = 0.0
+    t_done: float = 0.0
+
+
+def footprint(analysis, P, nsets=2):
+    i = analysis.info
+    return P * i["bytes_per_shift"] + analysis.workspace_size(P) + 8 * nsets * i["nnz_lower"]
+
+
+class BatchRunner:
+    """Runs density matrices of a list of jobs.  analyses are cached per job
+    (symbolic analysis once per pattern, as in an SCF cycle)."""
+
+    def __init__(self, jobs, budget_bytes=200 * 2**30, nstreams=4, device="cuda",
+                 keep_outputs=False):
+        import torch
+        self.torch = torch
+        self.jobs = list(jobs)
+        self.budget = int(budget_bytes)
+        self.device = device
+        self.keep = keep_outputs
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstreams))]
+        for j in self.jobs:
+            if j.analysis is None:
+                j.analysis = B.Analysis.from_system(j.system)
+            j.analysis.bind(device)
+            j.footprint = footprint(j.analysis, j.poles, j.nsets)
+            j.flops = j.poles * (j.analysis.info["flops_factor"] + j.analysis.info["flops_selinv"])
+            if j.footprint > self.budget:
+                raise B.PxsError("BatchRunner", B.PXS_ENOMEM,
+                                 f"job of {j.footprint / 2**30:.1f} GiB exceeds the budget")
+        self._H = {}
+        self._S = {}
+
+    def _values(self, j):
+        torch = self.torch
+        k = id(j)
+        if k not in self._H:
+            self._H[k] = torch.from_numpy(j.system.hval).to(self.device)
+            self._S[k] = torch.from_numpy(j.system.sval).to(self.device)
+        return self._H[k], self._S[k]
+
+    def run(self):
+        """Executes every job once; returns wall seconds."""
+        torch = self.torch
+        order = sorted(self.jobs, key=lambda j: -j.flops)
+        pending = list(order)
+        active = []     # (job, stream index, event, plan, tensors)
+        used = 0
+        free_streams = list(range(len(self.streams)))
+        busy = {}
+        t0 = time.perf_counter()
+        while pending or active:
+            launched = False
+            while pending and free_streams and used + pending[0].footprint <= self.budget:
+                j = pending.pop(0)
+                si = free_streams.pop(0)
+                st = self.streams[si]
+                with torch.cuda.stream(st):
+                    H, S = self._values(j)
+                    L, W = j.analysis.buffers(j.poles, device=self.device)
+                    plan = B.Plan(j.analysis, H, S, j.poles, nsets=j.nsets, L=L, work=W, device=self.device)
+                    sh, wt = B.poles(j.beta, 1.0 + abs(j.mu), j.mu, j.poles, j.nsets)
+                    j.t_submit = time.perf_counter()
+                    plan.run(sh, wt, stream=st, sync=False)
+                    ev = torch.cuda.Event()
+                    ev.record(st)
+                active.append((j, si, ev, plan, (L, W)))
+                used += j.footprint
+                launched = True
+            if not active:
+                if pending and not launched:
+                    raise B.PxsError("BatchRunner", B.PXS_ENOMEM, "cannot admit the next job")
+                continue
+            # wait for the earliest-submitted active job
+            j, si, ev, plan, bufs = active.pop(0)
+            ev.synchronize()
+            j.t_done = time.perf_counter()
+            j.traces, j.info = plan.results(stream=self.streams[si])
+            if self.keep:
+                j.out = plan.out.view(j.nsets, -1).clone()
+            del plan, bufs
+            used -= j.footprint
+            free_streams.append(si)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def total_flops(self):
+        return sum(j.flops for j in self.jobs)
+
+    def total_solves(self):
+        return sum(j.poles for j in self.jobs)
+
+
+def per_pole_loop(analysis, H, S, shifts, weights, device="cuda"):
+    """The plain per-pole loop on the same kernels: one shift per
+    factorization, no batching and no graphs; returns the pole sums."""
+    import torch
+    nsets = weights.shape[0]
+    nnz = analysis.info["nnz_lower"]
+    acc = torch.zeros(nsets, nnz, dtype=torch.float64, device=device)
+    L, W = analysis.buffers(1, device=device)
+    for l in range(shifts.shape[0]):
+        f = B.Factorization(analysis, H, S, shifts[l:l + 1], L=L, work=W)
+        f.selinv()
+        out, _ = f.pole_sum(weights[:, l:l + 1], traces=False)
+        acc += out
+    return acc

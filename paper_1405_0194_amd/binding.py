@@ -71,6 +71,10 @@ def load():
         "pxs_inertia": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
         "pxs_density_matrix": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
                                          C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
+        "pxs_plan_create": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P]),
+        "pxs_plan_run": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+        "pxs_plan_results": (C.c_int, [_P, _P, _P, _P]),
+        "pxs_plan_free": (None, [_P]),
         "pxs_profile_begin": (C.c_int, [C.c_int32]),
         "pxs_profile_end": (C.c_int, [_P, _P, _P]),
         "pxs_free_symbolic": (None, [_P]),
@@ -107,6 +111,28 @@ def _stream(stream=None):
 
 def _dptr(t):
     return _P(t.data_ptr())
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def _require(t, nbytes, what):
+    """Caller buffers go to the kernels as raw pointers: check them here."""
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what}: needs a contiguous device tensor")
+    if _nbytes(t) < nbytes:
+        raise ValueError(f"{what}: {_nbytes(t)} bytes, needs {nbytes}")
+    if t.data_ptr() % 256:
+        raise ValueError(f"{what}: must be 256-byte aligned")
+
+
+def _require_values(analysis, H, S):
+    import torch
+    nnz = analysis.info["nnz_lower"]
+    for t, name in ((H, "H values"), (S, "S values")):
+        if t.dtype != torch.float64 or t.numel() != nnz or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous float64 device tensor of {nnz} entries")
 
 
 # --------------------------------------------------------------------------
@@ -212,6 +238,9 @@ class Factorization:
         self.nshift = nshift
         if L is None or work is None:
             L, work = analysis.buffers(nshift)
+        _require_values(analysis, H, S)
+        _require(L, nshift * analysis.info["bytes_per_shift"], "factor storage")
+        _require(work, analysis.workspace_size(nshift), "workspace")
         self.L, self.work = L, work
         self.H, self.S = H, S   # keep the device value arrays alive
         self.info = np.zeros(nshift, dtype=np.int64)
@@ -240,24 +269,83 @@ class Factorization:
         _check("pxs_get_selected", self._lib.pxs_get_selected(self._h, l, _dptr(out), _stream(stream)))
         return out
 
-    def pole_sum(self, weights, stream=None, out=None):
+    def pole_sum(self, weights, stream=None, out=None, traces=True):
         """weights: (nsets, nshift) complex.  Returns (out (nsets, nnz), traces
-        array (nsets, 2) = [Tr(G S), Tr(G H)])."""
+        array (nsets, 2) = [Tr(G S), Tr(G H)], or None without traces)."""
         import torch
         weights = np.ascontiguousarray(weights, dtype=np.complex128)
         nsets = weights.shape[0]
         nnz = self.analysis.info["nnz_lower"]
         if out is None:
             out = torch.empty(nsets * nnz, dtype=torch.float64, device=self.L.device)
+        _require(out, 8 * nsets * nnz, "pole-sum output")
+        if weights.shape != (nsets, self.nshift):
+            raise ValueError("weights must be (nsets, nshift)")
         tr = np.zeros(2 * nsets)
-        _check("pxs_pole_sum", self._lib.pxs_pole_sum(self._h, nsets, _ptr(weights), _dptr(out), _ptr(tr),
-                                                       _stream(stream)))
-        return out.view(nsets, nnz), tr.reshape(nsets, 2)
+        _check("pxs_pole_sum", self._lib.pxs_pole_sum(self._h, nsets, _ptr(weights), _dptr(out),
+                                                       _ptr(tr) if traces else None, _stream(stream)))
+        return out.view(nsets, nnz), (tr.reshape(nsets, 2) if traces else None)
 
     def __del__(self):
         try:
             if getattr(self, "_h", None):
                 self._lib.pxs_free_numeric(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+class Plan:
+    """A graph-captured density matrix for a fixed batch size on fixed
+    buffers: run() uploads a pole table and replays the graph."""
+
+    def __init__(self, analysis: Analysis, H, S, nshift, nsets=2, L=None, work=None, device="cuda",
+                 out=None, accumulate=False):
+        import torch
+        lib = load()
+        self._lib = lib
+        self.analysis = analysis.bind()
+        self.nshift, self.nsets = int(nshift), int(nsets)
+        if L is None or work is None:
+            L, work = analysis.buffers(nshift)
+        _require_values(analysis, H, S)
+        _require(L, self.nshift * analysis.info["bytes_per_shift"], "factor storage")
+        _require(work, analysis.workspace_size(self.nshift), "workspace")
+        self.L, self.work, self.H, self.S = L, work, H, S
+        if out is None:
+            out = torch.empty(nsets * analysis.info["nnz_lower"], dtype=torch.float64, device=L.device)
+        _require(out, 8 * nsets * analysis.info["nnz_lower"], "pole-sum output")
+        self.out = out
+        h = _P()
+        _check("pxs_plan_create", lib.pxs_plan_create(analysis._h, _dptr(H), _dptr(S), self.nshift, self.nsets,
+                                                       _dptr(L), _dptr(work), _dptr(self.out),
+                                                       1 if accumulate else 0, C.byref(h)))
+        self._h = h
+
+    def run(self, shifts, weights, stream=None, sync=True):
+        """Returns (out view (nsets, nnz), traces (nsets, 2) or None, info)."""
+        shifts = np.ascontiguousarray(shifts, dtype=np.complex128)
+        weights = np.ascontiguousarray(weights, dtype=np.complex128).reshape(self.nsets, self.nshift)
+        tr = np.zeros(2 * self.nsets) if sync else None
+        info = np.zeros(self.nshift, dtype=np.int64) if sync else None
+        code = self._lib.pxs_plan_run(self._h, _ptr(shifts), _ptr(weights), _ptr(tr) if sync else None,
+                                      _ptr(info) if sync else None, _stream(stream))
+        _check("pxs_plan_run", code, allow=(PXS_OK, PXS_TINY_PIVOT))
+        nnz = self.analysis.info["nnz_lower"]
+        return self.out.view(self.nsets, nnz), (tr.reshape(self.nsets, 2) if sync else None), info
+
+    def results(self, stream=None):
+        """(traces (nsets, 2), info) of the last run (synchronises stream)."""
+        tr = np.zeros(2 * self.nsets)
+        info = np.zeros(self.nshift, dtype=np.int64)
+        _check("pxs_plan_results", self._lib.pxs_plan_results(self._h, _ptr(tr), _ptr(info), _stream(stream)),
+               allow=(PXS_OK, PXS_TINY_PIVOT))
+        return tr.reshape(self.nsets, 2), info
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                self._lib.pxs_plan_free(self._h)
                 self._h = None
         except Exception:
             pass
@@ -272,6 +360,9 @@ def inertia(analysis: Analysis, H, S, eps, L=None, work=None, stream=None):
     q = eps.shape[0]
     if L is None or work is None:
         L, work = analysis.buffers(q, real=True)
+    _require_values(analysis, H, S)
+    _require(L, q * analysis.info["bytes_per_shift"] // 2, "factor storage")
+    _require(work, analysis.workspace_size(q, real=True), "workspace")
     neg = np.zeros(q, dtype=np.int64)
     info = np.zeros(q, dtype=np.int64)
     code = lib.pxs_inertia(analysis._h, _dptr(H), _dptr(S), q, _ptr(eps), _dptr(L), _dptr(work),
@@ -289,6 +380,9 @@ def density_matrix(analysis: Analysis, H, S, beta, dE, mu, P, nsets=2, L=None, w
     analysis.bind()
     if L is None or work is None:
         L, work = analysis.buffers(P)
+    _require_values(analysis, H, S)
+    _require(L, P * analysis.info["bytes_per_shift"], "factor storage")
+    _require(work, analysis.workspace_size(P), "workspace")
     nnz = analysis.info["nnz_lower"]
     out = torch.empty(nsets * nnz, dtype=torch.float64, device=L.device)
     tr = np.zeros(2 * nsets)

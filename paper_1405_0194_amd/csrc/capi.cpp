@@ -29,6 +29,15 @@ struct pxs_numeric_s {
   bool selinv_done = false;
 };
 
+struct pxs_plan_s {
+  const pxs::Symbolic* S = nullptr;
+  int32_t nshift = 0, nsets = 0;
+  void* work = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<double> shifts, weights;   // host staging (sources of the uploads)
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -329,6 +338,93 @@ pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double
   if (shifts) std::memcpy(shifts, sh.data(), sizeof(pxs_c64) * P);
   if (weights) std::memcpy(weights, wt.data(), sizeof(pxs_c64) * nsets * P);
   return piv;
+}
+
+pxs_status pxs_plan_create(pxs_symbolic sym, const double* Hval, const double* Sval, int32_t nshift,
+                           int32_t nsets, void* Lbuf, void* work, double* out, int32_t flags,
+                           pxs_plan* plan) {
+  pxs_status s0 = check_numeric_args(sym, Hval, Sval, nshift, Lbuf, work);
+  if (s0 != PXS_OK) return s0;
+  if (!out || !plan || nsets < 1 || nsets > 4 || (flags & ~PXS_PLAN_ACCUMULATE)) return PXS_EINVAL;
+  *plan = nullptr;
+  pxs_plan_s* p = new (std::nothrow) pxs_plan_s;
+  if (!p) return PXS_ENOMEM;
+  p->S = &sym->S;
+  p->nshift = nshift;
+  p->nsets = nsets;
+  p->work = work;
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e);
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  int k = 0;
+  if (e == hipSuccess) {
+    k = pxs::run_factor_kernels<true>(sym->S, Hval, Sval, nshift, Lbuf, work, cs);
+    if (k == 0) k = pxs::run_selinv(sym->S, nshift, Lbuf, work, cs);
+    if (k == 0)
+      k = pxs::run_pole_sum_kernels(sym->S, nshift, Lbuf, work, Hval, Sval, nsets, out,
+                                    (flags & PXS_PLAN_ACCUMULATE) ? 1 : 0, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+    if (k == 0 && e2 != hipSuccess) k = (int)e2;
+  } else {
+    k = (int)e;
+  }
+  if (k == 0) k = (int)hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  hipStreamDestroy(cs);
+  if (k != 0) {
+    if (p->graph) hipGraphDestroy(p->graph);
+    delete p;
+    return hip_fail(k);
+  }
+  *plan = p;
+  return PXS_OK;
+}
+
+pxs_status pxs_plan_run(pxs_plan plan, const pxs_c64* shifts, const pxs_c64* weights, double* traces,
+                        int64_t* info, void* stream) {
+  if (!plan || !shifts || !weights) return PXS_EINVAL;
+  for (int32_t l = 0; l < plan->nshift; ++l)
+    if (!std::isfinite(shifts[l].re) || !std::isfinite(shifts[l].im)) return PXS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  plan->shifts.assign((const double*)shifts, (const double*)shifts + 2 * plan->nshift);
+  plan->weights.assign((const double*)weights, (const double*)weights + 2 * plan->nsets * plan->nshift);
+  int k = pxs::upload_shifts(plan->nshift, plan->shifts.data(), plan->work, st);
+  if (k == 0) k = pxs::upload_weights(plan->nshift, plan->nsets, plan->weights.data(), plan->work, st);
+  if (k == 0) k = (int)hipGraphLaunch(plan->exec, st);
+  if (k != 0) return hip_fail(k);
+  if (traces || info) return pxs_plan_results(plan, traces, info, stream);
+  return PXS_OK;
+}
+
+pxs_status pxs_plan_results(pxs_plan plan, double* traces, int64_t* info, void* stream) {
+  if (!plan) return PXS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  double t8[8];
+  std::vector<int64_t> inf(plan->nshift);
+  hipError_t he = hipMemcpyAsync(t8, (char*)plan->work + pxs::WK_TRACES, sizeof(t8), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(inf.data(), (char*)plan->work + pxs::WK_INFO, sizeof(int64_t) * plan->nshift,
+                        hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(he);
+  if (traces)
+    for (int g = 0; g < 2 * plan->nsets; ++g) traces[g] = t8[g];
+  bool tiny = false;
+  for (int32_t l = 0; l < plan->nshift; ++l) {
+    if (info) info[l] = inf[l];
+    tiny = tiny || inf[l] != 0;
+  }
+  return tiny ? PXS_TINY_PIVOT : PXS_OK;
+}
+
+void pxs_plan_free(pxs_plan plan) {
+  if (!plan) return;
+  if (plan->exec) hipGraphExecDestroy(plan->exec);
+  if (plan->graph) hipGraphDestroy(plan->graph);
+  delete plan;
 }
 
 pxs_status pxs_profile_begin(int32_t kernel) {

@@ -31,6 +31,15 @@ int profile_end(double* ms, int64_t* launches, double* work);
 template <bool CPLX>
 int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
                const double* shifts_host, void* L, void* work, hipStream_t st);
+// Kernel-only parts (no host copies), capturable into a HIP graph; the
+// shifts and weights are read from the workspace.
+template <bool CPLX>
+int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int nshift, void* L,
+                       void* work, hipStream_t st);
+int run_pole_sum_kernels(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
+                         const double* Sv, int nsets, double* out, int accumulate, hipStream_t st);
+int upload_shifts(int nshift, const double* shifts_host, void* work, hipStream_t st);
+int upload_weights(int nshift, int nsets, const double* weights_host, void* work, hipStream_t st);
 int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st);
 int run_pole_sum(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
                  const double* Sv, int nsets, const double* weights_host, double* out,

@@ -819,7 +819,7 @@ __global__ void __launch_bounds__(NT) k_pole_sum(const double* __restrict__ L, i
                                                  const int32_t* __restrict__ ediag, int64_t nnz,
                                                  const double* __restrict__ H,
                                                  const double* __restrict__ S, double* out,
-                                                 double* partial) {
+                                                 double* partial, int accumulate) {
   __shared__ double red[8][NT];
   double tr[8];
   for (int q = 0; q < 8; ++q) tr[q] = 0.0;
@@ -835,7 +835,8 @@ __global__ void __launch_bounds__(NT) k_pole_sum(const double* __restrict__ L, i
     }
     const double mult = ediag[k] ? 1.0 : 2.0;
     for (int g = 0; g < nsets; ++g) {
-      out[(int64_t)g * nnz + k] = acc[g];
+      // accumulate: add to the sums of earlier pole chunks (traces stay per chunk)
+      out[(int64_t)g * nnz + k] = accumulate ? out[(int64_t)g * nnz + k] + acc[g] : acc[g];
       tr[2 * g] += mult * acc[g] * S[k];
       tr[2 * g + 1] += mult * acc[g] * H[k];
     }
@@ -896,6 +897,11 @@ struct ProfScope {
   int err = 0;
   ProfScope(int kernel, hipStream_t s, double work) : st(s), on(g_prof.kernel == kernel && kernel != KC_NONE) {
     if (!on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+      on = false;   // no event nodes inside captured graphs
+      return;
+    }
     while (g_prof.ev.size() < g_prof.used + 2) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) { on = false; err = 1; return; }
@@ -991,13 +997,30 @@ int profile_end(double* ms, int64_t* launches, double* work) {
   return 0;
 }
 
+int upload_shifts(int nshift, const double* shifts_host, void* work, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync((char*)work + WK_SHIFTS, shifts_host, sizeof(double) * 2 * nshift,
+                                hipMemcpyHostToDevice, st);
+  return (int)e;
+}
+
+int upload_weights(int nshift, int nsets, const double* weights_host, void* work, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync((char*)work + WK_WEIGHTS, weights_host,
+                                sizeof(double) * 2 * nsets * nshift, hipMemcpyHostToDevice, st);
+  return (int)e;
+}
+
 template <bool CPLX>
 int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
                const double* shifts_host, void* L, void* work, hipStream_t st) {
+  int e = upload_shifts(nshift, shifts_host, work, st);
+  if (e != 0) return e;
+  return run_factor_kernels<CPLX>(S, H, Sv, nshift, L, work, st);
+}
+
+template <bool CPLX>
+int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int nshift, void* L,
+                       void* work, hipStream_t st) {
   char* w = (char*)work;
-  hipError_t e = hipMemcpyAsync(w + WK_SHIFTS, shifts_host, sizeof(double) * 2 * nshift,
-                                hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return (int)e;
   hipLaunchKernelGGL(k_zero_i64, dim3((2 * MAX_SHIFTS + NT - 1) / NT), dim3(NT), 0, st,
                      (int64_t*)(w + WK_INFO), 2 * MAX_SHIFTS);
   PXS_CHECK_LAUNCH();
@@ -1063,6 +1086,8 @@ int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
 
 template int run_factor<true>(const Symbolic&, const double*, const double*, int, const double*, void*, void*, hipStream_t);
 template int run_factor<false>(const Symbolic&, const double*, const double*, int, const double*, void*, void*, hipStream_t);
+template int run_factor_kernels<true>(const Symbolic&, const double*, const double*, int, void*, void*, hipStream_t);
+template int run_factor_kernels<false>(const Symbolic&, const double*, const double*, int, void*, void*, hipStream_t);
 
 int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st) {
   Common c = make_common(S, L, work);
@@ -1112,10 +1137,14 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
 int run_pole_sum(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
                  const double* Sv, int nsets, const double* weights_host, double* out,
                  hipStream_t st) {
+  int e = upload_weights(nshift, nsets, weights_host, work, st);
+  if (e != 0) return e;
+  return run_pole_sum_kernels(S, nshift, L, work, H, Sv, nsets, out, 0, st);
+}
+
+int run_pole_sum_kernels(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
+                         const double* Sv, int nsets, double* out, int accumulate, hipStream_t st) {
   char* w = (char*)work;
-  hipError_t e = hipMemcpyAsync(w + WK_WEIGHTS, weights_host, sizeof(double) * 2 * nsets * nshift,
-                                hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return (int)e;
   const char* m = (const char*)S.dmaps;
   const int nb = blocks_for(S.nnz_lower, POLESUM_BLOCKS);
   // bytes: one complex per entry and shift, offsets, flags, H, S, nsets outputs
@@ -1123,7 +1152,7 @@ int run_pole_sum(const Symbolic& S, int nshift, const void* L, void* work, const
   hipLaunchKernelGGL(k_pole_sum, dim3(nb), dim3(NT), 0, st, (const double*)L, S.nnzL_store, nshift,
                      (const double*)(w + WK_WEIGHTS), nsets, (const int64_t*)(m + S.o_entry_off),
                      (const int32_t*)(m + S.o_entry_diag), S.nnz_lower, H, Sv, out,
-                     (double*)(w + WK_POLESUM_PART));
+                     (double*)(w + WK_POLESUM_PART), accumulate);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, st, (const double*)(w + WK_POLESUM_PART), nb,
                      (double*)(w + WK_TRACES));
   PXS_CHECK_LAUNCH();

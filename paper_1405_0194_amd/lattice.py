@@ -154,12 +154,15 @@ def _pairs_within(coords, cutoff, cell_vectors, periodic_flags):
 
 
 def make_system(kind: str, dims, orb: int, cutoff: float, seed: int,
-                periodic: bool = True) -> System:
+                periodic: bool = True, dilute: float = 0.0) -> System:
     """Build one synthetic pencil.
 
     kind: "chain" (dims = natoms, open ends), "honeycomb" (dims = (nx, ny)
     cells of 2 atoms) or "cubic" (dims = (nx, ny, nz)).  ``periodic`` applies
     to honeycomb/cubic; an axis with fewer than 5 cells is left open.
+    ``dilute`` removes that fraction of the off-site pairs (drawn after the
+    blocks, so the other draws do not change), which gives systems of the
+    same size distinct sparsity patterns.
     """
     if kind == "chain":
         nat = int(dims)
@@ -194,6 +197,10 @@ def make_system(kind: str, dims, orb: int, cutoff: float, seed: int,
     Hb = G[:, 0] * scale
     Sb = 0.1 * G[:, 1] * scale
     onsite = I == J
+    if dilute > 0.0:
+        keep = onsite | (rng.uniform(size=npair) >= dilute)
+        I, J, D, Hb, Sb, onsite = I[keep], J[keep], D[keep], Hb[keep], Sb[keep], onsite[keep]
+        npair = I.shape[0]
     Hb[onsite] = 0.5 * (Hb[onsite] + np.transpose(Hb[onsite], (0, 2, 1)))
     So = 0.5 * (Sb[onsite] + np.transpose(Sb[onsite], (0, 2, 1)))
     idx = np.arange(orb)
@@ -348,7 +355,7 @@ def serving_requests(count: int, seed: int = CONFIG_SEED_BASE + 4,
             k = int(rng.choice(len(ks), p=pk)) + 1
             kind = kinds[int(rng.integers(0, 3))]
             dims, orb, cut = _dims_for(kind, size_unit * k)
-            s = make_system(kind, dims, orb, cut, seed * 100000 + r)
+            s = make_system(kind, dims, orb, cut, seed * 100000 + r, dilute=0.02)
             recent.append(s)
             recent = recent[-8:]
             eps = np.sort(rng.uniform(mu - 0.1, mu + 0.1, size=16))

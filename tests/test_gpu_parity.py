@@ -306,3 +306,32 @@ def test_full_size_honeycomb_bench_configuration(torch_cuda):
     say("traces", tr, "bound", bound)
     assert abs(tr[0, 1] - tr[1, 0]) <= bound
     assert 0.0 < tr[0, 0] < 2.0 * s.n
+
+
+def test_graph_plan_replays_match_eager(torch_cuda):
+    """The captured graph replayed several times (with eager library work and
+    synchronisations in between, new pole tables and new H values) gives the
+    eager result bit for bit every time."""
+    torch = torch_cuda
+    from paper_1405_0194_amd import binding as B
+    s = lattice.make_system("honeycomb", (6, 5), 13, 3.0, 31)
+    a = B.Analysis.from_system(s)
+    H = _dev(torch, s.hval)
+    S = _dev(torch, s.sval)
+    P = 20
+    say("case: graph plan replays")
+    plan = B.Plan(a, H, S, P, nsets=2)
+    rng = np.random.default_rng(2)
+    for rep in range(4):
+        mu = float(rng.uniform(-0.1, 0.1))
+        if rep == 2:
+            H.copy_(_dev(torch, s.hval * (1.0 + 1e-3 * rng.standard_normal(s.nnz_lower))))
+        sh, wt = B.poles(BETA, 1.0 + abs(mu), mu, P, 2)
+        out_g, tr_g, info = plan.run(sh, wt)
+        out_g = out_g.cpu().numpy().copy()
+        # eager library work on other buffers between replays
+        out_e, tr_e, info_e, _, _ = B.density_matrix(a, H, S, BETA, 1.0 + abs(mu), mu, P, nsets=2)
+        torch.cuda.synchronize()
+        assert np.array_equal(out_g, out_e.cpu().numpy()), rep
+        assert np.array_equal(tr_g, tr_e), rep
+        assert np.all(info == 0)
