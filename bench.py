@@ -188,6 +188,9 @@ def main():
     ap.add_argument("--profile-kernel", default="selinv_off")
     ap.add_argument("--compare-perpole", type=int, default=0,
                     help="also time the plain per-pole loop on this many shifts")
+    ap.add_argument("--tile-rows", type=int, default=0, help="rows per tile of the panel products (64/128)")
+    ap.add_argument("--panel-width", type=int, default=0)
+    ap.add_argument("--leaf-cols", type=int, default=0)
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--kmax", type=int, default=16, help="serve: largest size class (k * 1000)")
     args = ap.parse_args()
@@ -229,7 +232,8 @@ def main():
     dE = 1.0 + abs(mu)
     beta = lattice.BETA_300K
     t_an = time.perf_counter()
-    a = B.Analysis.from_system(s)
+    a = B.Analysis.from_system(s, tile_rows=args.tile_rows, panel_width=args.panel_width,
+                               leaf_cols=args.leaf_cols)
     t_an = time.perf_counter() - t_an
     a.bind()
     H = torch.from_numpy(s.hval).to(dev)

@@ -70,7 +70,10 @@ typedef struct {
                            batch); bounds the dense Z_CC workspace */
   double pivot_tol;     /* |d_k| < pivot_tol * (max|H| + |w| max|S|) flags a
                            tiny pivot (0: 1e-14) */
-  double reserved1[3];
+  int32_t tile_rows;    /* rows per workgroup tile of the panel products:
+                           64 or 128 (0: 64) */
+  int32_t reserved2;
+  double reserved1[2];
 } pxs_options;
 
 typedef struct {

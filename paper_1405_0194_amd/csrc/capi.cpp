@@ -116,6 +116,8 @@ pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, 
     if (opt->pivot_tol > 0) o.pivot_tol = opt->pivot_tol;
     if (opt->selinv_chunk < 0) return PXS_EINVAL;
     o.selinv_chunk = opt->selinv_chunk;
+    if (opt->tile_rows != 0 && opt->tile_rows != 64 && opt->tile_rows != 128) return PXS_EINVAL;
+    if (opt->tile_rows) o.tile_rows = opt->tile_rows;
     if (o.ordering != 0 && o.ordering != 1) return PXS_EINVAL;
     if (o.panel_width > 64) return PXS_EINVAL;
   }

@@ -272,6 +272,110 @@ __device__ __forceinline__ void xcd_remap(int& x, int& y) {
   y = logical / nx;
 }
 
+// Double-buffered variant: the chunk in registers is committed to the other
+// LDS buffer right after the MFMAs of the current chunk are issued, so the
+// LDS writes and the next fetch overlap the matrix-core work and one barrier
+// per chunk suffices (it orders both "commit before use" and "use before
+// overwrite", since each buffer is rewritten one iteration after its use).
+template <bool CPLX, int NTILE>
+struct Stage2 {
+  Stage<CPLX, NTILE> buf[2];
+};
+
+template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF>
+__device__ __forceinline__ void gemm_pipe2(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NTILE>& s, int kb, int ke,
+                                           GA ga, GB gb, BF bfast) {
+  using G = Geo<NTILE>;
+  if (kb >= ke) return;
+  cplx ra[G::XA], rb[G::XB];
+  bool fb = bfast(kb);
+  fetch<64, G::XA, AFAST>(ra, kb, ga);
+  fetch_rt<NTILE, G::XB>(rb, kb, gb, fb);
+  commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra);
+  commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb, fb);
+  if (kb + KC < ke) {
+    fb = bfast(kb + KC);
+    fetch<64, G::XA, AFAST>(ra, kb + KC, ga);
+    fetch_rt<NTILE, G::XB>(rb, kb + KC, gb, fb);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int k0 = kb; k0 < ke; k0 += KC) {
+    mfma_chunk<CPLX, NTILE>(acc, s.buf[cur]);
+    if (k0 + KC < ke) {
+      Stage<CPLX, NTILE>& nb = s.buf[cur ^ 1];
+      commit<CPLX, 64, G::XA, AFAST>(&nb.a_re[0][0], &nb.a_im[0][0], ra);
+      commit_rt<CPLX, NTILE, G::XB>(&nb.b_re[0][0], &nb.b_im[0][0], rb, fb);
+      if (k0 + 2 * KC < ke) {
+        fb = bfast(k0 + 2 * KC);
+        fetch<64, G::XA, AFAST>(ra, k0 + 2 * KC, ga);
+        fetch_rt<NTILE, G::XB>(rb, k0 + 2 * KC, gb, fb);
+      }
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+// Two-chunk-deep prefetch on top of the double-buffered LDS: two register
+// sets alternate (the loop is unrolled by two so both stay in registers),
+// so a chunk's global loads have two chunks of matrix-core time to land.
+//   prologue: R0 <- c0, R1 <- c1, commit R0 -> buf0, R0 <- c2
+//   even c:   mfma(buf0); commit R1 (c+1) -> buf1; R1 <- c+3
+//   odd  c:   mfma(buf1); commit R0 (c+1) -> buf0; R0 <- c+3
+// with one barrier after each step.
+template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF>
+__device__ __forceinline__ void gemm_pipe3(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NTILE>& s, int kb, int ke,
+                                           GA ga, GB gb, BF bfast) {
+  using G = Geo<NTILE>;
+  if (kb >= ke) return;
+  const int nc = (ke - kb + KC - 1) / KC;
+  cplx ra0[G::XA], rb0[G::XB], ra1[G::XA], rb1[G::XB];
+  bool fb0 = bfast(kb), fb1 = false;
+  fetch<64, G::XA, AFAST>(ra0, kb, ga);
+  fetch_rt<NTILE, G::XB>(rb0, kb, gb, fb0);
+  if (nc > 1) {
+    fb1 = bfast(kb + KC);
+    fetch<64, G::XA, AFAST>(ra1, kb + KC, ga);
+    fetch_rt<NTILE, G::XB>(rb1, kb + KC, gb, fb1);
+  }
+  commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra0);
+  commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb0, fb0);
+  if (nc > 2) {
+    fb0 = bfast(kb + 2 * KC);
+    fetch<64, G::XA, AFAST>(ra0, kb + 2 * KC, ga);
+    fetch_rt<NTILE, G::XB>(rb0, kb + 2 * KC, gb, fb0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nc; c += 2) {
+    mfma_chunk<CPLX, NTILE>(acc, s.buf[0]);
+    if (c + 1 < nc) {
+      commit<CPLX, 64, G::XA, AFAST>(&s.buf[1].a_re[0][0], &s.buf[1].a_im[0][0], ra1);
+      commit_rt<CPLX, NTILE, G::XB>(&s.buf[1].b_re[0][0], &s.buf[1].b_im[0][0], rb1, fb1);
+      if (c + 3 < nc) {
+        const int k3 = kb + (c + 3) * KC;
+        fb1 = bfast(k3);
+        fetch<64, G::XA, AFAST>(ra1, k3, ga);
+        fetch_rt<NTILE, G::XB>(rb1, k3, gb, fb1);
+      }
+    }
+    __syncthreads();
+    if (c + 1 >= nc) break;
+    mfma_chunk<CPLX, NTILE>(acc, s.buf[1]);
+    if (c + 2 < nc) {
+      commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra0);
+      commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb0, fb0);
+      if (c + 4 < nc) {
+        const int k4 = kb + (c + 4) * KC;
+        fb0 = bfast(k4);
+        fetch<64, G::XA, AFAST>(ra0, k4, ga);
+        fetch_rt<NTILE, G::XB>(rb0, k4, gb, fb0);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 struct RowsFast {
   __device__ bool operator()(int) const { return false; }
 };
@@ -467,11 +571,14 @@ __global__ void __launch_bounds__(NT) k_diag(Common c, PanelK p) {
 }
 
 // L_Bp = A_Bp L_pp^{-T} D^{-1}: P[c][i] = sum_k Linv[c][k] A[i][k], then / d_c.
-constexpr int TN = 128;   // rows per workgroup of the panel products
+// Panel products run on tiles of 64 x TNv (TNv = 64 or 128 rows, a runtime
+// option); with double-buffered LDS a 128-row tile uses 100 KB (one
+// workgroup per CU), a 64-row tile 67 KB (two per CU).
+#define PXS_LB(TNv) __launch_bounds__(NT, (TNv) == 64 ? 2 : 1)
 
-template <bool CPLX>
-__global__ void __launch_bounds__(NT, 2) k_trsm(Common c, PanelK p) {
-  __shared__ Stage<CPLX, TN> s;
+template <bool CPLX, int TN>
+__global__ void PXS_LB(TN) k_trsm(Common c, PanelK p) {
+  __shared__ Stage2<CPLX, TN> s;
   __shared__ cplx dinv[64];
   int bx, by;
   xcd_remap(bx, by);
@@ -486,7 +593,7 @@ __global__ void __launch_bounds__(NT, 2) k_trsm(Common c, PanelK p) {
   }
   Acc<CPLX, TN> acc;
   acc.zero();
-  gemm_pipe<CPLX, TN, false>(
+  gemm_pipe3<CPLX, TN, false>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[c][k]: column k of the diagonal block
         if (m >= p.wp || kg >= p.wp || m < kg) return cplx{0.0, 0.0};
@@ -508,9 +615,9 @@ __global__ void __launch_bounds__(NT, 2) k_trsm(Common c, PanelK p) {
 // Left-looking update of panel p from the earlier columns of its own
 // supernode: A[r][c] -= sum_{k < p0} L[r][k] d_k L[c][k] for rows r >= p0 of
 // the row list and the panel's columns c.  P[c][r] = sum_k (d_k L[c][k]) L[r][k].
-template <bool CPLX>
-__global__ void __launch_bounds__(NT, 2) k_int_update(Common c, PanelK p) {
-  __shared__ Stage<CPLX, TN> s;
+template <bool CPLX, int TN>
+__global__ void PXS_LB(TN) k_int_update(Common c, PanelK p) {
+  __shared__ Stage2<CPLX, TN> s;
   int bx, by;
   xcd_remap(bx, by);
   const int sh = by;
@@ -520,7 +627,7 @@ __global__ void __launch_bounds__(NT, 2) k_int_update(Common c, PanelK p) {
   const int64_t cbase = p.off + p.p0;        // element (row p0, column 0)
   Acc<CPLX, TN> acc;
   acc.zero();
-  gemm_pipe<CPLX, TN, false>(
+  gemm_pipe3<CPLX, TN, false>(
       acc, s, 0, p.p0,
       [&](int m, int kg) -> cplx {   // d_k L[p0 + c][k]
         if (m >= p.wp || kg >= p.p0) return cplx{0.0, 0.0};
@@ -559,9 +666,9 @@ __device__ __forceinline__ void tri_index(int b, int& ti, int& tj) {
 // maps (B = row-list positions from p0 + wp on).  Used once per supernode
 // with K = all of its columns (p0 = 0, wp = w_J, B = the rows below it).
 // P[j][i] = sum_k (d_k L[j][k]) L[i][k].
-template <bool CPLX>
-__global__ void __launch_bounds__(NT, 2) k_update(Common c, PanelK p) {
-  __shared__ Stage<CPLX, TN> s;
+template <bool CPLX, int TN>
+__global__ void PXS_LB(TN) k_update(Common c, PanelK p) {
+  __shared__ Stage2<CPLX, TN> s;
   int bx, by;
   xcd_remap(bx, by);
   const int sh = by;
@@ -577,7 +684,7 @@ __global__ void __launch_bounds__(NT, 2) k_update(Common c, PanelK p) {
   const int kb = p.p0, ke = p.p0 + p.wp;
   Acc<CPLX, TN> acc;
   acc.zero();
-  gemm_pipe<CPLX, TN, false>(
+  gemm_pipe3<CPLX, TN, false>(
       acc, s, kb, ke,
       [&](int m, int kg) -> cplx {
         const int jg = j0 + m;
@@ -614,8 +721,9 @@ __device__ __forceinline__ double* wbase(const Common& c, int sh) {
 }
 
 // W = L_Bp Linv: P[c][i] = sum_k Linv[k][c] L[i][k]; W stored W[c * nb + i].
-__global__ void __launch_bounds__(NT, 2) k_lhat(Common c, PanelK p) {
-  __shared__ Stage<true, TN> s;
+template <int TN>
+__global__ void PXS_LB(TN) k_lhat(Common c, PanelK p) {
+  __shared__ Stage2<true, TN> s;
   int bx, by;
   xcd_remap(bx, by);
   const int sh = p.sh0 + by;
@@ -626,7 +734,7 @@ __global__ void __launch_bounds__(NT, 2) k_lhat(Common c, PanelK p) {
   const int64_t rbase = dbase + p.wp;
   Acc<true, TN> acc;
   acc.zero();
-  gemm_pipe<true, TN, true>(
+  gemm_pipe3<true, TN, true>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[k][c]: column c of the diagonal block, rows k
         if (m >= p.wp || kg >= p.wp || kg < m) return cplx{0.0, 0.0};
@@ -649,8 +757,9 @@ __global__ void __launch_bounds__(NT, 2) k_lhat(Common c, PanelK p) {
 // part inside the supernode's own columns is read from the supernode's
 // storage (column min(i, k), row max(i, k)), the part in the rows below it
 // from the dense copy G of Z_CC made by k_gather_cc.
-__global__ void __launch_bounds__(NT, 2) k_selinv_off(Common c, PanelK p) {
-  __shared__ Stage<true, TN> s;
+template <int TN>
+__global__ void PXS_LB(TN) k_selinv_off(Common c, PanelK p) {
+  __shared__ Stage2<true, TN> s;
   int bx, by;
   xcd_remap(bx, by);
   const int sh = p.sh0 + by;
@@ -661,7 +770,7 @@ __global__ void __launch_bounds__(NT, 2) k_selinv_off(Common c, PanelK p) {
   const int base = p.p0 + p.wp;
   Acc<true, TN> acc;
   acc.zero();
-  gemm_pipe<true, TN, true>(
+  gemm_pipe3<true, TN, true>(
       acc, s, 0, p.nb,
       [&](int m, int kg) -> cplx {
         if (m >= p.wp || kg >= p.nb) return cplx{0.0, 0.0};
@@ -732,8 +841,8 @@ __global__ void __launch_bounds__(NT) k_gather_cc(Common c, PanelK p) {
 }
 
 // Partial W^T Z_Bp over k in [split * 512, ...): P[c][r] = sum_k Z[k][c] W[k][r].
-__global__ void __launch_bounds__(NT, 2) k_selinv_diag_partial(Common c, PanelK p) {
-  __shared__ Stage<true, TM> s;
+__global__ void PXS_LB(64) k_selinv_diag_partial(Common c, PanelK p) {
+  __shared__ Stage2<true, TM> s;
   int bx, by;
   xcd_remap(bx, by);
   const int sh = p.sh0 + by;
@@ -746,7 +855,7 @@ __global__ void __launch_bounds__(NT, 2) k_selinv_diag_partial(Common c, PanelK 
   const int kb = sp * 512, ke = min(p.nb, kb + 512);
   Acc<true, TM> acc;
   acc.zero();
-  gemm_pipe<true, TM, true>(
+  gemm_pipe3<true, TM, true>(
       acc, s, kb, ke,
       [&](int m, int kg) -> cplx {
         if (m >= p.wp || kg >= ke) return cplx{0.0, 0.0};
@@ -1046,6 +1155,7 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
   }
   PXS_CHECK_LAUNCH();
   Common c = make_common(S, L, work);
+  const int TR = S.tile_rows;
   const double fm = CPLX ? 8.0 : 2.0;   // flops per multiply-add
   const size_t np = S.panels.size();
   for (size_t ip = 0; ip < np; ++ip) {
@@ -1055,16 +1165,22 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
       // left-looking: the panel's rows receive the earlier columns of its supernode
       const int nrows = k.ld - k.p0;
       ProfScope ps(KC_UPDATE, st, fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0);
-      hipLaunchKernelGGL(k_int_update<CPLX>, dim3((nrows + TN - 1) / TN, nshift), dim3(NT), 0, st, c, k);
+      if (TR == 64)
+        hipLaunchKernelGGL((k_int_update<CPLX, 64>), dim3((nrows + 63) / 64, nshift), dim3(NT), 0, st, c, k);
+      else
+        hipLaunchKernelGGL((k_int_update<CPLX, 128>), dim3((nrows + 127) / 128, nshift), dim3(NT), 0, st, c, k);
     }
     {
       ProfScope ps(KC_DIAG, st, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0);
       hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NT), 0, st, c, k);
     }
     if (k.nb > 0) {
-      const int nt = (k.nb + TN - 1) / TN;
+      const int nt = (k.nb + TR - 1) / TR;
       ProfScope ps(KC_TRSM, st, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
-      hipLaunchKernelGGL(k_trsm<CPLX>, dim3(nt, nshift), dim3(NT), 0, st, c, k);
+      if (TR == 64)
+        hipLaunchKernelGGL((k_trsm<CPLX, 64>), dim3(nt, nshift), dim3(NT), 0, st, c, k);
+      else
+        hipLaunchKernelGGL((k_trsm<CPLX, 128>), dim3(nt, nshift), dim3(NT), 0, st, c, k);
     }
     const bool last = (ip + 1 == np) || (S.panels[ip + 1].J != P.J);
     const int32_t w = S.sfirst[P.J + 1] - S.sfirst[P.J];
@@ -1075,9 +1191,12 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
       u.p0 = 0;
       u.wp = w;
       u.nb = below;
-      const int ntj = (below + TM - 1) / TM, nti = (below + TN - 1) / TN;
+      const int ntj = (below + TM - 1) / TM, nti = (below + TR - 1) / TR;
       ProfScope ps(KC_UPDATE, st, fm * nshift * (double)below * (below + 1) / 2.0 * w);
-      hipLaunchKernelGGL(k_update<CPLX>, dim3(ntj * nti, nshift), dim3(NT), 0, st, c, u);
+      if (TR == 64)
+        hipLaunchKernelGGL((k_update<CPLX, 64>), dim3(ntj * nti, nshift), dim3(NT), 0, st, c, u);
+      else
+        hipLaunchKernelGGL((k_update<CPLX, 128>), dim3(ntj * nti, nshift), dim3(NT), 0, st, c, u);
     }
     PXS_CHECK_LAUNCH();
   }
@@ -1091,6 +1210,7 @@ template int run_factor_kernels<false>(const Symbolic&, const double*, const dou
 
 int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st) {
   Common c = make_common(S, L, work);
+  const int TR = S.tile_rows;
   c.G = (double*)((char*)work + S.work_fixed + (int64_t)nshift * S.work_per_shift);
   const int chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
   // supernodes from the root down; within a supernode, panels right to left
@@ -1111,14 +1231,20 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
         PanelK k = panel_args(S, S.panels[q]);
         k.sh0 = sh0;
         if (k.nb > 0) {
-          const int nt = (k.nb + TN - 1) / TN;
+          const int nt = (k.nb + TR - 1) / TR;
           {
             ProfScope ps(KC_LHAT, st, 8.0 * ns * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
-            hipLaunchKernelGGL(k_lhat, dim3(nt, ns), dim3(NT), 0, st, c, k);
+            if (TR == 64)
+              hipLaunchKernelGGL(k_lhat<64>, dim3(nt, ns), dim3(NT), 0, st, c, k);
+            else
+              hipLaunchKernelGGL(k_lhat<128>, dim3(nt, ns), dim3(NT), 0, st, c, k);
           }
           {
             ProfScope ps(KC_SELINV_OFF, st, 8.0 * ns * (double)k.nb * k.nb * k.wp);
-            hipLaunchKernelGGL(k_selinv_off, dim3(nt, ns), dim3(NT), 0, st, c, k);
+            if (TR == 64)
+              hipLaunchKernelGGL(k_selinv_off<64>, dim3(nt, ns), dim3(NT), 0, st, c, k);
+            else
+              hipLaunchKernelGGL(k_selinv_off<128>, dim3(nt, ns), dim3(NT), 0, st, c, k);
           }
           {
             ProfScope ps(KC_SELINV_DIAG, st, 8.0 * ns * (double)k.nb * k.wp * k.wp);

@@ -68,11 +68,13 @@ struct Symbolic {
   // of a SelInv chunk (selinv_chunk shifts, 0 = the whole batch).
   int64_t work_fixed = 0, work_per_shift = 0, gather_per_shift = 0;
   int32_t selinv_chunk = 0;
+  int32_t tile_rows = 64;           // rows per workgroup tile of the panel products (64 or 128)
   int32_t max_below_super = 0;      // max over supernodes of ld - w
 };
 
 struct AnalyzeOptions {
   int selinv_chunk = 0;
+  int tile_rows = 64;
   int ordering = 0;
   int leaf_cols = 128;
   int panel_width = 64;

@@ -538,6 +538,7 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
     S.max_below_super = std::max(S.max_below_super, S.ld[J] - (S.sfirst[J + 1] - S.sfirst[J]));
   S.gather_per_shift = (16 * (int64_t)S.max_below_super * S.max_below_super + 255) / 256 * 256;
   S.selinv_chunk = std::max(0, opt.selinv_chunk);
+  S.tile_rows = (opt.tile_rows == 128) ? 128 : 64;
   return 0;
 }
 
