@@ -122,7 +122,9 @@ def run_batch(args):
     items = lattice.batch_systems()
     jobs = [Job(system=s, poles=P, mu=0.0) for s, P in items]
     print(f"# batch: {len(jobs)} systems generated in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
-    br = BatchRunner(jobs, budget_bytes=250 * 2**30, nstreams=4)
+    from paper_1405_0194_amd import tune
+    tuned = tune.load_cache() or None
+    br = BatchRunner(jobs, budget_bytes=250 * 2**30, nstreams=4, tuned=tuned)
     for i in range(args.warmup):
         print(f"# warmup {i}: {br.run():.2f}s", file=sys.stderr, flush=True)
     times = []
@@ -132,7 +134,7 @@ def run_batch(args):
     elapsed = sum(times)
     solves = br.total_solves() * args.steps
     flops = br.total_flops() * args.steps
-    seq = BatchRunner(jobs, budget_bytes=250 * 2**30, nstreams=1)
+    seq = BatchRunner(jobs, budget_bytes=250 * 2**30, nstreams=1, tuned=tuned)
     t1 = seq.run()
     print(f"# one stream: {t1:.2f}s", file=sys.stderr, flush=True)
     res = dict(value=round(solves / elapsed, 4), ms_per_step=round(1e3 * elapsed / args.steps, 3),
@@ -142,7 +144,8 @@ def run_batch(args):
                           "p99": round(float(np.percentile(times, 99)), 4)},
                one_stream_pole_solves_per_s=round(br.total_solves() / t1, 4),
                config={"workload": MULTI["batch"], "systems": len(jobs), "pole_solves_per_step": br.total_solves(),
-                       "tflop_per_step": round(br.total_flops() / 1e12, 2)})
+                       "tflop_per_step": round(br.total_flops() / 1e12, 2),
+                       "tuned_buckets": len(tuned or {})})
     return res
 
 
@@ -156,7 +159,8 @@ def run_serve(args):
 
     def make():
         return [Request(system=r["system"], mu=r["mu"], poles=40, eps=r["eps"]) for r in raw]
-    srv = Server(budget_bytes=250 * 2**30, nstreams=4)
+    from paper_1405_0194_amd import tune
+    srv = Server(budget_bytes=250 * 2**30, nstreams=4, tuned=tune.load_cache() or None)
     sat = srv.run(make(), realtime=False)         # saturated: everything queued at t = 0
     print(f"# saturated: {sat}", file=sys.stderr, flush=True)
     lam = sat["req_per_s"]
@@ -232,8 +236,12 @@ def main():
     dE = 1.0 + abs(mu)
     beta = lattice.BETA_300K
     t_an = time.perf_counter()
-    a = B.Analysis.from_system(s, tile_rows=args.tile_rows, panel_width=args.panel_width,
-                               leaf_cols=args.leaf_cols)
+    if args.tile_rows or args.panel_width or args.leaf_cols:
+        a = B.Analysis.from_system(s, tile_rows=args.tile_rows, panel_width=args.panel_width,
+                                   leaf_cols=args.leaf_cols)
+    else:
+        from paper_1405_0194_amd import tune
+        a = tune.tuned_analysis(s, lattice.CONFIG_POLES[cfg])
     t_an = time.perf_counter() - t_an
     a.bind()
     H = torch.from_numpy(s.hval).to(dev)

@@ -48,7 +48,7 @@ class BatchRunner:
     (symbolic analysis once per pattern, as in an SCF cycle)."""
 
     def __init__(self, jobs, budget_bytes=200 * 2**30, nstreams=4, device="cuda",
-                 keep_outputs=False):
+                 keep_outputs=False, tuned=None):
         import torch
         self.torch = torch
         self.jobs = list(jobs)
@@ -58,7 +58,11 @@ class BatchRunner:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstreams))]
         for j in self.jobs:
             if j.analysis is None:
-                j.analysis = B.Analysis.from_system(j.system)
+                if tuned is not None:
+                    from .tune import tuned_analysis
+                    j.analysis = tuned_analysis(j.system, j.poles, cache=tuned)
+                else:
+                    j.analysis = B.Analysis.from_system(j.system)
             j.analysis.bind(device)
             j.footprint = footprint(j.analysis, j.poles, j.nsets)
             j.flops = j.poles * (j.analysis.info["flops_factor"] + j.analysis.info["flops_selinv"])

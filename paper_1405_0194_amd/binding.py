@@ -56,6 +56,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # PyTorch brings its own HIP runtime; load it first so that the library
+    # resolves libamdhip64 to that same runtime (one runtime per process).
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     sig = {
         "pxs_poles": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, _P, _P]),

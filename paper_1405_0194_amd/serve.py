@@ -99,7 +99,7 @@ def resident_bytes(analysis, nshift, nsets=2):
 
 class Server:
     def __init__(self, budget_bytes=250 * 2**30, nstreams=4, max_patterns=64, device="cuda",
-                 keep_outputs=False):
+                 keep_outputs=False, tuned=None):
         import torch
         self.torch = torch
         self.budget = int(budget_bytes)
@@ -108,13 +108,14 @@ class Server:
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstreams))]
         self.analyses = OrderedDict()       # pattern key -> Analysis (LRU)
         self.max_patterns = max_patterns
+        self.tuned = tuned
         self.residents = OrderedDict()      # (key, P) -> Resident (LRU)
         self.used = 0
         self.stats = dict(symbolic_hits=0, symbolic_misses=0, plan_hits=0, plan_misses=0,
                           evictions=0, chunked=0, analyze_s=0.0)
 
     # ------------------------------------------------------------------ caches
-    def analysis(self, system, key=None):
+    def analysis(self, system, key=None, poles=40):
         key = key or pattern_key(system)
         a = self.analyses.get(key)
         if a is not None:
@@ -122,7 +123,11 @@ class Server:
             self.stats["symbolic_hits"] += 1
             return key, a
         t = time.perf_counter()
-        a = B.Analysis.from_system(system).bind(self.device)
+        if self.tuned:
+            from .tune import tuned_analysis
+            a = tuned_analysis(system, poles, cache=self.tuned).bind(self.device)
+        else:
+            a = B.Analysis.from_system(system).bind(self.device)
         self.stats["analyze_s"] += time.perf_counter() - t
         self.stats["symbolic_misses"] += 1
         self.analyses[key] = a
@@ -160,11 +165,11 @@ class Server:
         first = not req.key
         if first:
             req.key = pattern_key(req.system)
-            key, a = self.analysis(req.system, req.key)
+            key, a = self.analysis(req.system, req.key, req.poles)
         else:
             key, a = req.key, self.analyses.get(req.key)
             if a is None:
-                key, a = self.analysis(req.system, req.key)
+                key, a = self.analysis(req.system, req.key, req.poles)
         chunk = self.chunk_for(a, req.poles, req.nsets)
         rk = (key, req.poles, req.nsets, chunk)
         r = self.residents.get(rk)

@@ -1,0 +1,140 @@
+"""Autotuner for the supernode and tile shapes.
+
+The tunable knobs are options of the symbolic analysis: the largest
+nested-dissection leaf (leaf_cols, which sets how small the supernodes at
+the bottom of the tree get), the panel width (columns per factor/SelInv
+panel, the K-depth of the in-panel products) and the tile height of the
+panel products (64 or 128 rows per workgroup).  Shapes are grouped into
+buckets by structural features only (matrix size, fill of L, pole count), so
+any input -- not just the synthetic lattices -- maps to a bucket.  For each
+bucket the tuner times one density matrix per candidate (graph-captured plan,
+median of a few replays) and keeps the fastest in a JSON cache.
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import binding as B
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(HERE, "tuned.json")
+DEFAULTS = dict(leaf_cols=128, panel_width=64, tile_rows=64)
+CANDIDATES = dict(leaf_cols=(64, 128, 256), panel_width=(32, 64), tile_rows=(64, 128))
+
+
+def bucket(analysis, P):
+    """Shape bucket of an analysed pattern and pole count."""
+    i = analysis.info
+    n = max(1, i["n"])
+    fill = max(1.0, i["nnz_L_exact"] / n)
+    return f"n{int(round(math.log2(n)))}_f{int(round(math.log2(fill)))}_p{'hi' if P > 50 else 'lo'}"
+
+
+def load_cache(path=DEFAULT_CACHE):
+    if path and os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def tuned_analysis(system, P, cache=None, path=DEFAULT_CACHE):
+    """Analysis of the system with the tuned options of its bucket (the
+    default analysis when the bucket is untuned or tuned to the defaults)."""
+    cache = load_cache(path) if cache is None else cache
+    a = B.Analysis.from_system(system)
+    opts = cache.get(bucket(a, P), {}).get("options") if cache else None
+    if not opts or opts == DEFAULTS:
+        return a
+    return B.Analysis.from_system(system, **opts)
+
+
+def options_for(system, P, cache=None, path=DEFAULT_CACHE):
+    """Tuned analysis options for this system's bucket (defaults if the
+    bucket has not been tuned)."""
+    cache = load_cache(path) if cache is None else cache
+    if not cache:
+        return dict(DEFAULTS)
+    a = B.Analysis.from_system(system)
+    return dict(cache.get(bucket(a, P), {}).get("options", DEFAULTS))
+
+
+def time_candidate(system, P, opts, reps=3, device="cuda"):
+    import torch
+    a = B.Analysis.from_system(system, **opts).bind(device)
+    H = torch.from_numpy(system.hval).to(device)
+    S = torch.from_numpy(system.sval).to(device)
+    plan = B.Plan(a, H, S, P, nsets=2)
+    sh, wt = B.poles(B_BETA(), 1.0, 0.0, P, 2)
+    plan.run(sh, wt)                      # warm-up (also checks pivots)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan.run(sh, wt)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    del plan
+    return float(np.median(ts)), a
+
+
+def B_BETA():
+    from .lattice import BETA_300K
+    return BETA_300K
+
+
+def tune_system(system, P, cache, candidates=CANDIDATES, reps=3, log=sys.stderr):
+    """Tunes the bucket of one system (skips buckets already in the cache)."""
+    a0 = B.Analysis.from_system(system)
+    key = bucket(a0, P)
+    if key in cache:
+        return key, cache[key]
+    best = None
+    trials = []
+    names = sorted(candidates)
+    for vals in itertools.product(*(candidates[k] for k in names)):
+        opts = dict(zip(names, vals))
+        t, _ = time_candidate(system, P, opts, reps=reps)
+        trials.append(dict(options=opts, seconds=round(t, 6)))
+        if best is None or t < best[0]:
+            best = (t, opts)
+        print(f"# tune {key} {opts}: {t * 1e3:.2f} ms", file=log, flush=True)
+    d0 = next(tr["seconds"] for tr in trials if tr["options"] == DEFAULTS) if any(
+        tr["options"] == DEFAULTS for tr in trials) else None
+    cache[key] = dict(options=best[1], seconds=round(best[0], 6), default_seconds=d0,
+                      example=dict(kind=system.kind, n=system.n, poles=P), trials=trials)
+    return key, cache[key]
+
+
+def main():
+    ap = argparse.ArgumentParser(description="autotune supernode/tile shapes on the GPU")
+    ap.add_argument("--workload", default="batch", choices=("batch", "honeycomb", "serve"))
+    ap.add_argument("--out", default=DEFAULT_CACHE)
+    ap.add_argument("--max-systems", type=int, default=64)
+    args = ap.parse_args()
+    from . import lattice
+    cache = load_cache(args.out)
+    if args.workload == "honeycomb":
+        items = [(lattice.config_system(1), 60)]
+    elif args.workload == "batch":
+        items = lattice.batch_systems()
+    else:
+        items = [(r["system"], 40) for r in lattice.serving_requests(64, kmax=16) if not r["repeat"]]
+    for s, P in items[: args.max_systems]:
+        key, ent = tune_system(s, P, cache)
+        print(f"# {key}: {ent['options']} {ent['seconds'] * 1e3:.2f} ms (default {ent['default_seconds']})",
+              file=sys.stderr, flush=True)
+        with open(args.out, "w") as f:      # saved after every bucket
+            json.dump(cache, f, indent=1, sort_keys=True)
+    print(json.dumps({k: v["options"] for k, v in cache.items()}))
+
+
+if __name__ == "__main__":
+    main()
