@@ -195,6 +195,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per tile of the panel products (64/128)")
     ap.add_argument("--panel-width", type=int, default=0)
     ap.add_argument("--leaf-cols", type=int, default=0)
+    ap.add_argument("--selinv-streams", type=int, default=0)
+    ap.add_argument("--selinv-chunk", type=int, default=0)
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--kmax", type=int, default=16, help="serve: largest size class (k * 1000)")
     args = ap.parse_args()
@@ -236,9 +238,10 @@ def main():
     dE = 1.0 + abs(mu)
     beta = lattice.BETA_300K
     t_an = time.perf_counter()
-    if args.tile_rows or args.panel_width or args.leaf_cols:
+    if args.tile_rows or args.panel_width or args.leaf_cols or args.selinv_streams or args.selinv_chunk:
         a = B.Analysis.from_system(s, tile_rows=args.tile_rows, panel_width=args.panel_width,
-                                   leaf_cols=args.leaf_cols)
+                                   leaf_cols=args.leaf_cols, selinv_streams=args.selinv_streams,
+                                   selinv_chunk=args.selinv_chunk)
     else:
         from paper_1405_0194_amd import tune
         a = tune.tuned_analysis(s, lattice.CONFIG_POLES[cfg])

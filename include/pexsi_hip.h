@@ -72,7 +72,9 @@ typedef struct {
                            tiny pivot (0: 1e-14) */
   int32_t tile_rows;    /* rows per workgroup tile of the panel products:
                            64 or 128 (0: 64) */
-  int32_t reserved2;
+  int32_t selinv_streams; /* streams for independent subtrees in selected
+                           inversion, 1..8 (0: 4); the library creates them
+                           (default priority) on first use */
   double reserved1[2];
 } pxs_options;
 
@@ -131,9 +133,8 @@ pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind,
 
 pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info);
 
-/* Workspace bytes for a batch of nshift shifts: work_fixed + nshift *
- * work_per_shift, plus min(nshift, selinv_chunk or nshift) * gather_per_shift
- * unless `real` (inertia batches run no selected inversion). */
+/* Workspace bytes for a batch of nshift shifts (`real`: an inertia batch,
+ * which runs no selected inversion and needs less). */
 pxs_status pxs_workspace_size(pxs_symbolic sym, int32_t nshift, int32_t real, int64_t* bytes);
 
 /* Export of the analysis, for tests and tools (host arrays, any may be NULL):

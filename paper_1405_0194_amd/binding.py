@@ -32,7 +32,7 @@ class c64(C.Structure):
 class Options(C.Structure):
     _fields_ = [("ordering", C.c_int32), ("leaf_cols", C.c_int32), ("panel_width", C.c_int32),
                 ("selinv_chunk", C.c_int32), ("pivot_tol", C.c_double), ("tile_rows", C.c_int32),
-                ("reserved2", C.c_int32), ("reserved1", C.c_double * 2)]
+                ("selinv_streams", C.c_int32), ("reserved1", C.c_double * 2)]
 
 
 class SymInfo(C.Structure):
@@ -153,13 +153,13 @@ class Analysis:
     """Symbolic analysis handle (host), optionally bound to device maps."""
 
     def __init__(self, n, colptr, rowind, blkptr=None, coords=None, ordering=0, leaf_cols=0,
-                 panel_width=0, pivot_tol=0.0, selinv_chunk=0, tile_rows=0):
+                 panel_width=0, pivot_tol=0.0, selinv_chunk=0, tile_rows=0, selinv_streams=0):
         lib = load()
         self._lib = lib
         self.n = int(n)
         colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         rowind = np.ascontiguousarray(rowind, dtype=np.int32)
-        opt = Options(ordering, leaf_cols, panel_width, selinv_chunk, pivot_tol, tile_rows)
+        opt = Options(ordering, leaf_cols, panel_width, selinv_chunk, pivot_tol, tile_rows, selinv_streams)
         h = _P()
         nblk = 0
         bp = None

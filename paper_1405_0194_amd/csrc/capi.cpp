@@ -29,6 +29,8 @@ struct pxs_numeric_s {
   bool selinv_done = false;
 };
 
+extern "C" void pxs_plan_free(struct pxs_plan_s* plan);
+
 struct pxs_plan_s {
   const pxs::Symbolic* S = nullptr;
   int32_t nshift = 0, nsets = 0;
@@ -36,6 +38,7 @@ struct pxs_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<double> shifts, weights;   // host staging (sources of the uploads)
+  std::vector<hipEvent_t> events;        // fork/join events recorded in the capture
 };
 
 namespace {
@@ -118,6 +121,8 @@ pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, 
     o.selinv_chunk = opt->selinv_chunk;
     if (opt->tile_rows != 0 && opt->tile_rows != 64 && opt->tile_rows != 128) return PXS_EINVAL;
     if (opt->tile_rows) o.tile_rows = opt->tile_rows;
+    if (opt->selinv_streams < 0 || opt->selinv_streams > 8) return PXS_EINVAL;
+    if (opt->selinv_streams) o.selinv_streams = opt->selinv_streams;
     if (o.ordering != 0 && o.ordering != 1) return PXS_EINVAL;
     if (o.panel_width > 64) return PXS_EINVAL;
   }
@@ -153,7 +158,7 @@ pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info) {
   info->bytes_per_shift = 16 * S.nnzL_store;
   info->work_fixed = S.work_fixed;
   info->work_per_shift = S.work_per_shift;
-  info->work_bytes = S.work_fixed + S.work_per_shift + S.gather_per_shift;
+  info->work_bytes = pxs::selinv_work_bytes(S, 1);
   info->gather_per_shift = S.gather_per_shift;
   info->selinv_chunk = S.selinv_chunk;
   info->map_bytes = S.map_bytes;
@@ -166,12 +171,7 @@ pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info) {
 pxs_status pxs_workspace_size(pxs_symbolic sym, int32_t nshift, int32_t real, int64_t* bytes) {
   if (!sym || !bytes || nshift < 1 || nshift > pxs::MAX_SHIFTS) return PXS_EINVAL;
   const pxs::Symbolic& S = sym->S;
-  int64_t b = S.work_fixed + (int64_t)nshift * S.work_per_shift;
-  if (!real) {
-    const int32_t chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
-    b += (int64_t)chunk * S.gather_per_shift;
-  }
-  *bytes = b;
+  *bytes = real ? S.work_fixed + (int64_t)nshift * S.work_per_shift : pxs::selinv_work_bytes(S, nshift);
   return PXS_OK;
 }
 
@@ -202,6 +202,8 @@ pxs_status pxs_symbolic_bind(pxs_symbolic sym, void* maps, void* stream) {
   e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e);
   sym->S.dmaps = maps;
+  const int k = pxs::selinv_streams_ready(sym->S);
+  if (k != 0) return hip_fail(k);
   return PXS_OK;
 }
 
@@ -355,30 +357,33 @@ pxs_status pxs_plan_create(pxs_symbolic sym, const double* Hval, const double* S
   p->nshift = nshift;
   p->nsets = nsets;
   p->work = work;
-  hipStream_t cs = nullptr;
-  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e != hipSuccess) {
-    delete p;
-    return hip_fail(e);
+  // everything the capture needs is created before it starts
+  int k = pxs::selinv_streams_ready(sym->S);
+  for (int q = 0; k == 0 && q < pxs::selinv_event_count(sym->S); ++q) {
+    hipEvent_t ev;
+    k = (int)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (k == 0) p->events.push_back(ev);
   }
-  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-  int k = 0;
-  if (e == hipSuccess) {
-    k = pxs::run_factor_kernels<true>(sym->S, Hval, Sval, nshift, Lbuf, work, cs);
-    if (k == 0) k = pxs::run_selinv(sym->S, nshift, Lbuf, work, cs);
-    if (k == 0)
-      k = pxs::run_pole_sum_kernels(sym->S, nshift, Lbuf, work, Hval, Sval, nsets, out,
-                                    (flags & PXS_PLAN_ACCUMULATE) ? 1 : 0, cs);
-    hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
-    if (k == 0 && e2 != hipSuccess) k = (int)e2;
-  } else {
-    k = (int)e;
+  hipStream_t cs = nullptr;
+  if (k == 0) k = (int)hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (k == 0) {
+    k = (int)hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (k == 0) {
+      k = pxs::run_factor_kernels<true>(sym->S, Hval, Sval, nshift, Lbuf, work, cs);
+      if (k == 0) k = pxs::run_selinv(sym->S, nshift, Lbuf, work, cs, p->events.data());
+      if (k == 0)
+        k = pxs::run_pole_sum_kernels(sym->S, nshift, Lbuf, work, Hval, Sval, nsets, out,
+                                      (flags & PXS_PLAN_ACCUMULATE) ? 1 : 0, cs);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(cs, &g);
+      if (e2 == hipSuccess) p->graph = g;   // only a graph the capture produced is kept
+      if (k == 0 && e2 != hipSuccess) k = (int)e2;
+    }
   }
   if (k == 0) k = (int)hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-  hipStreamDestroy(cs);
+  if (cs) hipStreamDestroy(cs);
   if (k != 0) {
-    if (p->graph) hipGraphDestroy(p->graph);
-    delete p;
+    pxs_plan_free(p);
     return hip_fail(k);
   }
   *plan = p;
@@ -426,6 +431,7 @@ void pxs_plan_free(pxs_plan plan) {
   if (!plan) return;
   if (plan->exec) hipGraphExecDestroy(plan->exec);
   if (plan->graph) hipGraphDestroy(plan->graph);
+  for (hipEvent_t e : plan->events) hipEventDestroy(e);
   delete plan;
 }
 

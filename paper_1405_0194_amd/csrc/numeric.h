@@ -40,7 +40,15 @@ int run_pole_sum_kernels(const Symbolic& S, int nshift, const void* L, void* wor
                          const double* Sv, int nsets, double* out, int accumulate, hipStream_t st);
 int upload_shifts(int nshift, const double* shifts_host, void* work, hipStream_t st);
 int upload_weights(int nshift, int nsets, const double* weights_host, void* work, hipStream_t st);
-int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st);
+// events: nullptr (library pool) or selinv_event_count(S) events owned by
+// the caller (a graph plan).
+int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st,
+               hipEvent_t* events = nullptr);
+int selinv_event_count(const Symbolic& S);
+// creates the subtree streams (call outside any stream capture)
+int selinv_streams_ready(const Symbolic& S);
+// workspace bytes a batch of nshift complex shifts needs (factor + SelInv)
+int64_t selinv_work_bytes(const Symbolic& S, int nshift);
 int run_pole_sum(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
                  const double* Sv, int nsets, const double* weights_host, double* out,
                  hipStream_t st);

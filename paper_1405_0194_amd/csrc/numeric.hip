@@ -1208,54 +1208,156 @@ template int run_factor<false>(const Symbolic&, const double*, const double*, in
 template int run_factor_kernels<true>(const Symbolic&, const double*, const double*, int, void*, void*, hipStream_t);
 template int run_factor_kernels<false>(const Symbolic&, const double*, const double*, int, void*, void*, hipStream_t);
 
-int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st) {
-  Common c = make_common(S, L, work);
-  const int TR = S.tile_rows;
-  c.G = (double*)((char*)work + S.work_fixed + (int64_t)nshift * S.work_per_shift);
+// Streams and events owned by the library for the subtree-parallel SelInv
+// (created on first use on the current device, kept for the process).
+struct StreamPool {
+  int device = -1;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+};
+StreamPool g_pool;
+
+int ensure_pool(int nstreams, int nevents) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (g_pool.device != dev) {
+    g_pool.streams.clear();   // streams of another device are left alone
+    g_pool.events.clear();
+    g_pool.device = dev;
+  }
+  while ((int)g_pool.streams.size() < nstreams) {
+    hipStream_t s;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return (int)e;
+    g_pool.streams.push_back(s);
+  }
+  while ((int)g_pool.events.size() < nevents) {
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return (int)e;
+    g_pool.events.push_back(ev);
+  }
+  return 0;
+}
+
+int64_t selinv_work_bytes(const Symbolic& S, int nshift) {
   const int chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
-  // supernodes from the root down; within a supernode, panels right to left
-  int ip = (int)S.panels.size() - 1;
-  while (ip >= 0) {
-    const int J = S.panels[ip].J;
-    int first = ip;
-    while (first > 0 && S.panels[first - 1].J == J) --first;
-    for (int sh0 = 0; sh0 < nshift; sh0 += chunk) {
-      const int ns = std::min(chunk, nshift - sh0);
-      PanelK g = panel_args(S, S.panels[ip]);
+  int64_t g = 0;
+  for (int64_t b : S.gather_bytes) g += b;
+  return S.work_fixed + (int64_t)nshift * S.sel_nstreams * S.work_per_shift + (int64_t)chunk * g;
+}
+
+#define PXS_HIP(call)                      \
+  do {                                     \
+    hipError_t e_ = (call);                \
+    if (e_ != hipSuccess) return (int)e_;  \
+  } while (0)
+
+int selinv_streams_ready(const Symbolic& S) {
+  // streams are created here, never inside a stream capture
+  return ensure_pool(S.sel_nstreams - 1, 0);
+}
+
+int selinv_event_count(const Symbolic& S) { return S.nsuper + S.sel_nstreams + 1; }
+
+int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st,
+               hipEvent_t* events) {
+  // inside a stream capture everything runs on the capturing stream: the
+  // subtree streams are used by eager runs only
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  PXS_HIP(hipStreamIsCapturing(st, &cap));
+  const bool single = (cap != hipStreamCaptureStatusNone) || S.sel_nstreams == 1;
+  const int NS = single ? 1 : S.sel_nstreams;
+  const int ns = S.nsuper;
+  const int TR = S.tile_rows;
+  int err = ensure_pool(NS - 1, events ? 0 : selinv_event_count(S));
+  if (err) return err;
+  std::vector<hipStream_t> strm(NS);
+  strm[0] = st;
+  for (int q = 1; q < NS; ++q) strm[q] = g_pool.streams[q - 1];
+  // events: the caller's (a graph plan keeps its own, since an event last
+  // recorded inside a capture must not be waited on outside it) or the pool's
+  hipEvent_t* ev = events ? events : g_pool.events.data();   // ev[J]: SelInv of J done
+  hipEvent_t* ev_join = ev + ns;                   // ev_join[q], q >= 1
+  hipEvent_t ev_fork = ev[ns + NS];
+  const int chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
+  // per-stream workspace views
+  std::vector<Common> cs(NS, make_common(S, L, work));
+  // workspace views (selinv_work_bytes): per-shift regions of all streams,
+  // then the dense Z_CC regions of all streams; one stream alone uses the
+  // first per-shift region and the whole Z_CC area with the largest stride
+  // (max_q gather_bytes[q] <= sum_q gather_bytes[q])
+  int64_t gofs = S.work_fixed + (int64_t)nshift * S.sel_nstreams * S.work_per_shift;
+  for (int q = 0; q < NS; ++q) {
+    cs[q].wfix = S.work_fixed + (int64_t)q * nshift * S.work_per_shift;
+    cs[q].G = (double*)((char*)work + gofs);
+    cs[q].gstride = (single ? S.gather_per_shift : S.gather_bytes[q]) / 8;
+    gofs += (int64_t)chunk * S.gather_bytes[q];
+  }
+  auto stream_of = [&](int J) { return single ? 0 : S.sel_stream[J]; };
+  // first panel of every supernode (panels are grouped by supernode, in order)
+  std::vector<int> pfirst(ns, 0);
+  for (int ip = (int)S.panels.size() - 1; ip >= 0; --ip) pfirst[S.panels[ip].J] = ip;
+
+  for (int sh0 = 0; sh0 < nshift; sh0 += chunk) {
+    const int nsh = std::min(chunk, nshift - sh0);
+    if (NS > 1) {
+      PXS_HIP(hipEventRecord(ev_fork, st));
+      for (int q = 1; q < NS; ++q) PXS_HIP(hipStreamWaitEvent(strm[q], ev_fork, 0));
+    }
+    // supernodes from the roots down; a child on another stream waits for
+    // its parent's event
+    for (int J = ns - 1; J >= 0; --J) {
+      const int q = stream_of(J);
+      hipStream_t sj = strm[q];
+      const Common& c = cs[q];
+      const int P = S.sparent[J];
+      if (P >= 0 && stream_of(P) != q) PXS_HIP(hipStreamWaitEvent(sj, ev[P], 0));
+      const int first = pfirst[J];
+      int last = first;
+      while (last + 1 < (int)S.panels.size() && S.panels[last + 1].J == J) ++last;
+      PanelK g = panel_args(S, S.panels[last]);
       g.sh0 = sh0;
       if (g.c > 0) {
         const int nt = (g.c + TM - 1) / TM;
-        hipLaunchKernelGGL(k_gather_cc, dim3(nt * (nt + 1) / 2, ns), dim3(NT), 0, st, c, g);
+        hipLaunchKernelGGL(k_gather_cc, dim3(nt * (nt + 1) / 2, nsh), dim3(NT), 0, sj, c, g);
       }
-      for (int q = ip; q >= first; --q) {
-        PanelK k = panel_args(S, S.panels[q]);
+      for (int ip = last; ip >= first; --ip) {
+        PanelK k = panel_args(S, S.panels[ip]);
         k.sh0 = sh0;
         if (k.nb > 0) {
           const int nt = (k.nb + TR - 1) / TR;
           {
-            ProfScope ps(KC_LHAT, st, 8.0 * ns * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
+            ProfScope ps(KC_LHAT, sj, 8.0 * nsh * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
             if (TR == 64)
-              hipLaunchKernelGGL(k_lhat<64>, dim3(nt, ns), dim3(NT), 0, st, c, k);
+              hipLaunchKernelGGL(k_lhat<64>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
             else
-              hipLaunchKernelGGL(k_lhat<128>, dim3(nt, ns), dim3(NT), 0, st, c, k);
+              hipLaunchKernelGGL(k_lhat<128>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
           }
           {
-            ProfScope ps(KC_SELINV_OFF, st, 8.0 * ns * (double)k.nb * k.nb * k.wp);
+            ProfScope ps(KC_SELINV_OFF, sj, 8.0 * nsh * (double)k.nb * k.nb * k.wp);
             if (TR == 64)
-              hipLaunchKernelGGL(k_selinv_off<64>, dim3(nt, ns), dim3(NT), 0, st, c, k);
+              hipLaunchKernelGGL(k_selinv_off<64>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
             else
-              hipLaunchKernelGGL(k_selinv_off<128>, dim3(nt, ns), dim3(NT), 0, st, c, k);
+              hipLaunchKernelGGL(k_selinv_off<128>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
           }
           {
-            ProfScope ps(KC_SELINV_DIAG, st, 8.0 * ns * (double)k.nb * k.wp * k.wp);
-            hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, ns), dim3(NT), 0, st, c, k);
+            ProfScope ps(KC_SELINV_DIAG, sj, 8.0 * nsh * (double)k.nb * k.wp * k.wp);
+            hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, nsh), dim3(NT), 0, sj, c, k);
           }
         }
-        hipLaunchKernelGGL(k_selinv_diag_final, dim3(1, ns), dim3(NT), 0, st, c, k);
+        hipLaunchKernelGGL(k_selinv_diag_final, dim3(1, nsh), dim3(NT), 0, sj, c, k);
         PXS_CHECK_LAUNCH();
       }
+      if (!single && S.cross_child[J]) PXS_HIP(hipEventRecord(ev[J], sj));
     }
-    ip = first - 1;
+    if (NS > 1) {
+      for (int q = 1; q < NS; ++q) {
+        PXS_HIP(hipEventRecord(ev_join[q], strm[q]));
+        PXS_HIP(hipStreamWaitEvent(st, ev_join[q], 0));
+      }
+    }
   }
   return 0;
 }

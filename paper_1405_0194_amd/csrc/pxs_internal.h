@@ -69,10 +69,20 @@ struct Symbolic {
   int64_t work_fixed = 0, work_per_shift = 0, gather_per_shift = 0;
   int32_t selinv_chunk = 0;
   int32_t tile_rows = 64;           // rows per workgroup tile of the panel products (64 or 128)
+
+  // Selected inversion runs independent subtrees on separate streams:
+  // sel_stream[J] in [0, sel_nstreams); a supernode waits for its parent
+  // when they are on different streams.  Each stream has its own per-shift
+  // region (work_per_shift) and dense Z_CC region (gather_bytes[s] per shift).
+  int32_t sel_nstreams = 1;
+  std::vector<int32_t> sel_stream;
+  std::vector<int64_t> gather_bytes;
+  std::vector<uint8_t> cross_child;  // J has a child on another stream
   int32_t max_below_super = 0;      // max over supernodes of ld - w
 };
 
 struct AnalyzeOptions {
+  int selinv_streams = 4;
   int selinv_chunk = 0;
   int tile_rows = 64;
   int ordering = 0;

@@ -537,6 +537,58 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
   for (int32_t J = 0; J < ns; ++J)
     S.max_below_super = std::max(S.max_below_super, S.ld[J] - (S.sfirst[J + 1] - S.sfirst[J]));
   S.gather_per_shift = (16 * (int64_t)S.max_below_super * S.max_below_super + 255) / 256 * 256;
+
+  // streams for selected inversion: walking the supernodal tree from the
+  // roots, a node's heaviest child stays on its stream, further children
+  // open new streams while there are free ones, else join the least loaded
+  {
+    const int NS = std::max(1, std::min(8, opt.selinv_streams));
+    std::vector<double> work(ns, 0.0), sub(ns, 0.0);
+    for (const Panel& P : S.panels) work[P.J] += (double)P.nb_rows * P.nb_rows * P.wp;
+    for (int32_t J = 0; J < ns; ++J) {
+      sub[J] += work[J];
+      if (S.sparent[J] >= 0) sub[S.sparent[J]] += sub[J];
+    }
+    S.sel_stream.assign(ns, 0);
+    S.cross_child.assign(ns, 0);
+    std::vector<double> load(NS, 0.0);
+    int used = 0;
+    std::vector<int32_t> roots;
+    for (int32_t J = ns - 1; J >= 0; --J)
+      if (S.sparent[J] < 0) roots.push_back(J);
+    auto pick = [&](double w) {
+      int s = 0;
+      if (used < NS) {
+        s = used++;
+      } else {
+        for (int t = 1; t < NS; ++t)
+          if (load[t] < load[s]) s = t;
+      }
+      load[s] += w;
+      return s;
+    };
+    for (int32_t r : roots) S.sel_stream[r] = pick(sub[r]);
+    for (int32_t J = ns - 1; J >= 0; --J) {
+      std::vector<int32_t> kids = children[J];
+      std::sort(kids.begin(), kids.end(), [&](int32_t a, int32_t b) { return sub[a] > sub[b]; });
+      for (size_t q = 0; q < kids.size(); ++q) {
+        if (q == 0) {
+          S.sel_stream[kids[q]] = S.sel_stream[J];
+        } else {
+          load[S.sel_stream[J]] -= sub[kids[q]];
+          S.sel_stream[kids[q]] = pick(sub[kids[q]]);
+        }
+        if (S.sel_stream[kids[q]] != S.sel_stream[J]) S.cross_child[J] = 1;
+      }
+    }
+    S.sel_nstreams = std::max(1, used);
+    S.gather_bytes.assign(S.sel_nstreams, 0);
+    for (int32_t J = 0; J < ns; ++J) {
+      const int64_t c = S.ld[J] - (S.sfirst[J + 1] - S.sfirst[J]);
+      int64_t& g = S.gather_bytes[S.sel_stream[J]];
+      g = std::max(g, (16 * c * c + 255) / 256 * 256);
+    }
+  }
   S.selinv_chunk = std::max(0, opt.selinv_chunk);
   S.tile_rows = (opt.tile_rows == 128) ? 128 : 64;
   return 0;

@@ -137,6 +137,8 @@ def test_inertia_counts_match_eigenvalues(torch_cuda):
     ("honeycomb", (7, 5), 4, 3.0, dict(ordering=1, leaf_cols=70)),
     ("cubic", (5, 5, 5), 13, 2.0, dict(selinv_chunk=7)),
     ("honeycomb", (6, 6), 13, 3.0, dict(tile_rows=128)),
+    ("honeycomb", (8, 7), 13, 3.0, dict(selinv_streams=1)),
+    ("cubic", (6, 5, 5), 13, 2.0, dict(selinv_streams=8, selinv_chunk=13)),
     ("chain", 301, 3, 2.0, dict(panel_width=7, leaf_cols=33, tile_rows=128)),
 ])
 def test_lattice_parity_several_tiles(torch_cuda, kind, dims, orb, cut, akw):
