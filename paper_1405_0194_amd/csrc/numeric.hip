@@ -487,17 +487,27 @@ __device__ __forceinline__ double* shift_base(const Common& c, int sh) {
   return c.L + (CPLX ? 2 : 1) * c.stride * sh;
 }
 
-// Dense LDL^T of the panel's wp x wp diagonal block, then L_pp^{-1} in place.
+// Dense LDL^T of the panel's wp x wp diagonal block in LDS, then L_pp^{-1}.
+// 512 threads: step k scales column k once (l[k][r] = a[r][k] / d_k) and
+// then updates the trailing triangle a[r][j] -= a[r][k] l[j][k] with eight
+// threads per row.  The unit-lower inverse is then computed column by
+// column, one thread per column and no barriers: column t of L^{-1} is
+// x_t = 1, x_i = -sum_{t <= k < i} L[i][k] x_k, reading L from `l` and
+// writing x into the (no longer needed) strict lower part of `a`.
+constexpr int NTD = 512;
+
 template <bool CPLX>
-__global__ void __launch_bounds__(NT) k_diag(Common c, PanelK p) {
-  __shared__ double a_re[64][LDP];   // a[col][row]
+__global__ void __launch_bounds__(NTD) k_diag(Common c, PanelK p) {
+  __shared__ double a_re[64][LDP];   // a[col][row]: working matrix, then L^{-1}
   __shared__ double a_im[CPLX ? 64 : 1][LDP];
+  __shared__ double l_re[64][LDP];   // l[col][row]: L (strict lower)
+  __shared__ double l_im[CPLX ? 64 : 1][LDP];
   const int sh = blockIdx.y;
   double* Ls = shift_base<CPLX>(c, sh);
   const int wp = p.wp;
   const int t = threadIdx.x;
   const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;
-  for (int idx = t; idx < wp * wp; idx += NT) {
+  for (int idx = t; idx < wp * wp; idx += NTD) {
     const int cc = idx / wp, r = idx % wp;
     cplx v{0.0, 0.0};
     if (r >= cc) v = ld_elem<CPLX>(Ls, dbase + (int64_t)cc * p.ld + r);
@@ -509,7 +519,7 @@ __global__ void __launch_bounds__(NT) k_diag(Common c, PanelK p) {
   const double thr = c.pivtol * (c.absmax[0] + (CPLX ? wabs : fabs(c.shifts[2 * sh])) * c.absmax[1]);
   int bad = 0;
   int neg = 0;
-  const int r = t & 63, cg = t >> 6;
+  const int r = t & 63, cg = t >> 6;   // eight threads per row
   for (int k = 0; k < wp; ++k) {
     const cplx d{a_re[k][k], CPLX ? a_im[k][k] : 0.0};
     if (t == 0) {
@@ -517,22 +527,20 @@ __global__ void __launch_bounds__(NT) k_diag(Common c, PanelK p) {
       if (!(ad >= thr) && bad == 0) bad = p.col0 + k + 1;
       if (!CPLX && d.re < 0.0) ++neg;
     }
-    const cplx id = CPLX ? cinv(d) : cplx{1.0 / d.re, 0.0};
-    if (r > k && r < wp) {
-      const cplx lrk{a_re[k][r], CPLX ? a_im[k][r] : 0.0};
-      for (int cc = k + 1 + cg; cc <= r; cc += 4) {
-        const cplx lck{a_re[k][cc], CPLX ? a_im[k][cc] : 0.0};
-        const cplx f = cmul(lrk, cmul(lck, id));
-        a_re[cc][r] -= f.re;
-        if (CPLX) a_im[cc][r] -= f.im;
-      }
+    if (t > k && t < wp) {
+      const cplx id = CPLX ? cinv(d) : cplx{1.0 / d.re, 0.0};
+      const cplx v = cmul(cplx{a_re[k][t], CPLX ? a_im[k][t] : 0.0}, id);
+      l_re[k][t] = v.re;
+      if (CPLX) l_im[k][t] = v.im;
     }
     __syncthreads();
-    if (t > k && t < wp) {
-      const cplx v{a_re[k][t], CPLX ? a_im[k][t] : 0.0};
-      const cplx s = cmul(v, id);
-      a_re[k][t] = s.re;
-      if (CPLX) a_im[k][t] = s.im;
+    if (r > k && r < wp) {
+      const cplx lrk{a_re[k][r], CPLX ? a_im[k][r] : 0.0};
+      for (int j = k + 1 + cg; j <= r; j += NTD / 64) {
+        const cplx f = cmul(lrk, cplx{l_re[k][j], CPLX ? l_im[k][j] : 0.0});
+        a_re[j][r] -= f.re;
+        if (CPLX) a_im[j][r] -= f.im;
+      }
     }
     __syncthreads();
   }
@@ -541,30 +549,20 @@ __global__ void __launch_bounds__(NT) k_diag(Common c, PanelK p) {
     if (bad) atomicCAS((unsigned long long*)&c.info[sh], 0ull, (unsigned long long)bad);
     if (!CPLX && neg) atomicAdd((unsigned long long*)&c.negc[sh], (unsigned long long)neg);
   }
-  // in-place inverse of the unit lower factor: column j of L^{-1} is
-  // x_i = -sum_{k=j+1..i} Linv[i][k] L[k][j] (Linv[i][i] = 1), using columns
-  // > j that are already inverted and the original column j.
-  for (int j = wp - 2; j >= 0; --j) {
-    cplx x{0.0, 0.0};
-    if (t > j && t < wp) {
-      cplx s{a_re[j][t], CPLX ? a_im[j][t] : 0.0};
-      for (int k = j + 1; k < t; ++k) {
-        const cplx li{a_re[k][t], CPLX ? a_im[k][t] : 0.0};
-        const cplx lk{a_re[j][k], CPLX ? a_im[j][k] : 0.0};
-        const cplx pr = cmul(li, lk);
-        s.re += pr.re;
-        s.im += pr.im;
+  if (t < wp) {
+    for (int i = t + 1; i < wp; ++i) {
+      cplx s{l_re[t][i], CPLX ? l_im[t][i] : 0.0};
+      for (int k = t + 1; k < i; ++k) {
+        const cplx q = cmul(cplx{l_re[k][i], CPLX ? l_im[k][i] : 0.0}, cplx{a_re[t][k], CPLX ? a_im[t][k] : 0.0});
+        s.re += q.re;
+        s.im += q.im;
       }
-      x = {-s.re, -s.im};
+      a_re[t][i] = -s.re;
+      if (CPLX) a_im[t][i] = -s.im;
     }
-    __syncthreads();
-    if (t > j && t < wp) {
-      a_re[j][t] = x.re;
-      if (CPLX) a_im[j][t] = x.im;
-    }
-    __syncthreads();
   }
-  for (int idx = t; idx < wp * wp; idx += NT) {
+  __syncthreads();
+  for (int idx = t; idx < wp * wp; idx += NTD) {
     const int cc = idx / wp, rr = idx % wp;
     if (rr >= cc) st_elem<CPLX>(Ls, dbase + (int64_t)cc * p.ld + rr, cplx{a_re[cc][rr], CPLX ? a_im[cc][rr] : 0.0});
   }
@@ -780,16 +778,14 @@ __global__ void PXS_LB(TN) k_selinv_off(Common c, PanelK p) {
         const int ig = i0 + n;
         if (kg >= p.nb || ig >= p.nb) return cplx{0.0, 0.0};
         const int qk = base + kg, qi = base + ig;
-        if (qk >= p.w && qi >= p.w) return ld_elem<true>(G, (int64_t)(qk - p.w) * p.c + (qi - p.w));
         const int lo = min(qi, qk), hi = max(qi, qk);
+        if (lo >= p.w) return ld_elem<true>(G, (int64_t)(lo - p.w) * p.c + (hi - p.w));
         return ld_elem<true>(Ls, p.off + (int64_t)lo * p.ld + hi);
       },
-      // rows are contiguous for each k when the whole chunk lies on or below
-      // the diagonal of the tile, or inside G; otherwise k is contiguous
-      [&](int k0) -> bool {
-        const bool rows = (i0 >= k0 + KC - 1) || (base + k0 >= p.w && base + i0 >= p.w);
-        return !rows;
-      });
+      // both sources are lower triangles stored by column: rows are
+      // contiguous for each k when the whole chunk lies on or below the
+      // diagonal of the tile; otherwise k is contiguous
+      [&](int k0) -> bool { return !(i0 >= k0 + KC - 1); });
   const int64_t rbase = p.off + (int64_t)p.p0 * p.ld + base;
   acc_foreach<true, TN>(acc, [&](int m, int n, cplx v) {
     const int ig = i0 + n;
@@ -797,12 +793,11 @@ __global__ void PXS_LB(TN) k_selinv_off(Common c, PanelK p) {
   });
 }
 
-// G = Z_CC: G[a + b c] = Z(w + a, w + b) for all a, b < c, from the
-// ancestors' storage through the maps (lower tiles read once, written to
-// both halves through an LDS transpose).
+// G = Z_CC, lower triangle: G[a + b c] = Z(w + a, w + b) for b <= a < c,
+// gathered from the ancestors' storage through the maps.  Each thread moves
+// 16 elements of a 64 x 64 tile: first all relative row positions, then all
+// values, then the stores, so the loads of a thread are in flight together.
 __global__ void __launch_bounds__(NT) k_gather_cc(Common c, PanelK p) {
-  __shared__ double t_re[64][LDP];   // t[b][a]
-  __shared__ double t_im[64][LDP];
   const int sh = p.sh0 + blockIdx.y;
   const double* Ls = shift_base<true>(c, sh);
   double* G = c.G + c.gstride * blockIdx.y;
@@ -813,30 +808,23 @@ __global__ void __launch_bounds__(NT) k_gather_cc(Common c, PanelK p) {
   const int64_t* cmap = c.colmap + p.cm;
   const int64_t* cseg = c.colseg + p.cm;
   const int t = threadIdx.x;
-#pragma unroll 4
+  const int a = a0 + (t & 63);
+  int64_t e[16];
+  bool ok[16];
+#pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const int la = t & 63, lb = (t >> 6) + 4 * j;
-    const int a = a0 + la, b = b0 + lb;
-    cplx v{0.0, 0.0};
-    if (a < cc && b < cc && a >= b) {
-      const int qa = w + a, qb = w + b;
-      v = ld_elem<true>(Ls, cmap[qb] + c.relpos[cseg[qb] + qa]);
-    }
-    t_re[lb][la] = v.re;
-    t_im[lb][la] = v.im;
+    const int b = b0 + (t >> 6) + 4 * j;
+    ok[j] = (a < cc && b < cc && a >= b);
+    e[j] = 0;
+    if (ok[j]) e[j] = cmap[w + b] + c.relpos[cseg[w + b] + w + a];
   }
-  __syncthreads();
-#pragma unroll 4
+  cplx v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = ok[j] ? ld_elem<true>(Ls, e[j]) : cplx{0.0, 0.0};
+#pragma unroll
   for (int j = 0; j < 16; ++j) {
-    const int la = t & 63, lb = (t >> 6) + 4 * j;
-    const int a = a0 + la, b = b0 + lb;
-    if (a < cc && b < cc && a >= b) st_elem<true>(G, (int64_t)b * cc + a, cplx{t_re[lb][la], t_im[lb][la]});
-  }
-#pragma unroll 4
-  for (int j = 0; j < 16; ++j) {
-    const int lb = t & 63, la = (t >> 6) + 4 * j;
-    const int a = a0 + la, b = b0 + lb;
-    if (a < cc && b < cc && a > b) st_elem<true>(G, (int64_t)a * cc + b, cplx{t_re[lb][la], t_im[lb][la]});
+    const int b = b0 + (t >> 6) + 4 * j;
+    if (ok[j]) st_elem<true>(G, (int64_t)b * cc + a, v[j]);
   }
 }
 
@@ -1172,7 +1160,7 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
     }
     {
       ProfScope ps(KC_DIAG, st, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0);
-      hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NT), 0, st, c, k);
+      hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NTD), 0, st, c, k);
     }
     if (k.nb > 0) {
       const int nt = (k.nb + TR - 1) / TR;
