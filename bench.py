@@ -67,6 +67,41 @@ def measured_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
+def traffic_from_counters(kernel, workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, commands):
+    """Writes the HBM bytes per launch of one kernel from four rocprofv3
+    --pmc runs (FETCH_SIZE, WRITE_SIZE of the workload; the same two counters
+    over a plain device copy of 1 GiB, which scale the counters to bytes)."""
+    import csv
+
+    def values(d, name_pred):
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            return [float(r["Counter_Value"]) for r in csv.DictReader(f) if name_pred(r["Kernel_Name"])]
+
+    gib = float(2**30)
+    def ours(n):
+        return n.split("<")[0].split("(")[0].strip() == "k_" + kernel
+
+    fk = values(fetch_dir, ours)
+    wk = values(write_dir, ours)
+    fc = values(copy_fetch_dir, lambda n: "copyBuffer" in n or "copy" in n.lower())
+    wc = values(copy_write_dir, lambda n: "copyBuffer" in n or "copy" in n.lower())
+    if not fk or len(fk) != len(wk) or not fc or not wc:
+        raise SystemExit("counter files do not match the kernel or hold no copy launch")
+    f_scale = gib / (1024.0 * sum(fc) / len(fc))   # bytes per counted KiB
+    w_scale = gib / (1024.0 * sum(wc) / len(wc))
+    fetch = 1024.0 * f_scale * sum(fk) / len(fk)
+    write = 1024.0 * w_scale * sum(wk) / len(wk)
+    out = {"kernel": kernel, "workload": workload, "launches": len(fk),
+           "fetch_bytes_per_launch": round(fetch), "write_bytes_per_launch": round(write),
+           "hbm_bytes_per_launch": round(fetch + write),
+           "fetch_counter_scale": round(f_scale, 4), "write_counter_scale": round(w_scale, 4),
+           "source_hash": kernel_source_hash(), "commands": commands}
+    p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    with open(p, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline(full_n, seconds_target=15.0):
     """The oracle as it stands: one pole-solve = dense inverse of H - w S.
     Timed on a smaller honeycomb sample and scaled by (N_sample / N)^3."""
@@ -197,6 +232,11 @@ def main():
     ap.add_argument("--leaf-cols", type=int, default=0)
     ap.add_argument("--selinv-streams", type=int, default=0)
     ap.add_argument("--selinv-chunk", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (for scaling the HBM byte counters)")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write profiles/<kernel>_<workload>_traffic.json from four rocprofv3 --pmc "
+                         "output folders and exit (no GPU use)")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--kmax", type=int, default=16, help="serve: largest size class (k * 1000)")
     args = ap.parse_args()
@@ -206,11 +246,33 @@ def main():
               "is not supported (multi-GPU pole sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
 
+    if args.traffic_from:
+        f, w, cf, cw = args.traffic_from
+        run = (f"python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --selinv-streams 1 "
+               f"--workload {args.workload}")
+        cmds = [f"rocprofv3 --pmc {c} --kernel-include-regex {args.profile_kernel} -T -f csv -d <dir> -o run "
+                f"-- {run}" for c in ("FETCH_SIZE", "WRITE_SIZE")]
+        cmds += [f"rocprofv3 --pmc {c} -T -f csv -d <dir> -o run -- python3 bench.py --copy-calibration"
+                 for c in ("FETCH_SIZE", "WRITE_SIZE")]
+        traffic_from_counters(args.profile_kernel, args.workload, f, w, cf, cw, cmds)
+        return
+
     import numpy as np
     import torch
     from paper_1405_0194_amd import binding as B
     from paper_1405_0194_amd import lattice
     globals()["np"] = np
+
+    if args.copy_calibration:
+        # a plain copy kernel of known size: 1 GiB read and 1 GiB written per launch
+        x = torch.ones(2**27, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": 2**30, "copy_bytes_written_per_launch": 2**30,
+                          "launches": 3}), flush=True)
+        return
 
     if args.workload in MULTI:
         torch.cuda.set_device(0)
@@ -276,7 +338,7 @@ def main():
         print(f"# step {i}: {lat[-1]:.3f}s  Tr(GS)={tr[0, 0]:.6f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kms, klaunch, kwork = B.profile_end()
+    kms, klaunch, kwork, kbytes = B.profile_end(with_bytes=True)
 
     # phase breakdown on one extra (untimed) step
     phases = {}
@@ -326,7 +388,8 @@ def main():
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                      "avg_launch_ms": round(avg_ms, 4), "launches": klaunch,
-                     "traffic": traffic},
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": round(kbytes / max(klaunch, 1))},
     }
     if args.profile_kernel in ("assemble", "pole_sum"):
         gbs = (kwork / max(klaunch, 1)) / (avg_ms / 1e3) / 1e9 if klaunch else 0.0

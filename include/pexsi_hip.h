@@ -235,12 +235,14 @@ void pxs_plan_free(pxs_plan plan);
  *         4 SelInv diagonal-block product, 5 L-hat product, 6 diagonal-block
  *         LDL^T, 7 assembly, 8 pole sum.
  * pxs_profile_end synchronises those events and returns the summed kernel
- * time (ms), the number of launches and their algorithmic flops (complex
+ * time (ms), the number of launches, their algorithmic flops (complex
  * multiply-add = 8 flops, on the stored supernodal structure, no tile
- * padding) or, for kernels 7 and 8, their algorithmic HBM bytes.
+ * padding; for kernels 7 and 8 their algorithmic HBM bytes instead) and, in
+ * `bytes` (nullable), their algorithmic HBM bytes: every operand read once
+ * and every result written once.
  * Process-wide state; not thread safe.  PXS_ESTATE if no profile is open. */
 pxs_status pxs_profile_begin(int32_t kernel);
-pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work);
+pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work, double* bytes);
 
 /* Text of the last HIP or validation error seen by this thread (diagnostics). */
 const char* pxs_last_error(void);

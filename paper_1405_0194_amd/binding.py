@@ -80,7 +80,7 @@ def load():
         "pxs_plan_results": (C.c_int, [_P, _P, _P, _P]),
         "pxs_plan_free": (None, [_P]),
         "pxs_profile_begin": (C.c_int, [C.c_int32]),
-        "pxs_profile_end": (C.c_int, [_P, _P, _P]),
+        "pxs_profile_end": (C.c_int, [_P, _P, _P, _P]),
         "pxs_free_symbolic": (None, [_P]),
         "pxs_free_numeric": (None, [_P]),
         "pxs_status_string": (C.c_char_p, [C.c_int]),
@@ -409,10 +409,14 @@ def profile_begin(kernel: str):
     _check("pxs_profile_begin", load().pxs_profile_begin(KERNELS[kernel]))
 
 
-def profile_end():
-    """Returns (total kernel ms, launches, algorithmic flops or bytes)."""
+def profile_end(with_bytes=False):
+    """Returns (total kernel ms, launches, algorithmic flops or bytes), plus
+    the algorithmic HBM bytes when with_bytes is set."""
     ms = C.c_double()
     n = C.c_int64()
     w = C.c_double()
-    _check("pxs_profile_end", load().pxs_profile_end(C.byref(ms), C.byref(n), C.byref(w)))
+    b = C.c_double()
+    _check("pxs_profile_end", load().pxs_profile_end(C.byref(ms), C.byref(n), C.byref(w), C.byref(b)))
+    if with_bytes:
+        return ms.value, n.value, w.value, b.value
     return ms.value, n.value, w.value

@@ -441,9 +441,11 @@ pxs_status pxs_profile_begin(int32_t kernel) {
   return PXS_OK;
 }
 
-pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work) {
+pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work, double* bytes) {
   if (!total_ms || !launches || !work) return PXS_EINVAL;
-  int e = pxs::profile_end(total_ms, launches, work);
+  double b = 0.0;
+  int e = pxs::profile_end(total_ms, launches, work, &b);
+  if (bytes) *bytes = b;
   if (e != 0) return hip_fail(e);
   return PXS_OK;
 }

@@ -984,7 +984,8 @@ struct Profiler {
   std::vector<hipEvent_t> ev;   // pool, reused across profiles
   size_t used = 0;
   int64_t launches = 0;
-  double work = 0.0;
+  double work = 0.0;    // algorithmic flops (bytes for the memory-bound classes)
+  double bytes = 0.0;   // algorithmic HBM bytes: operands read once, results written once
 };
 Profiler g_prof;
 
@@ -992,7 +993,8 @@ struct ProfScope {
   hipStream_t st;
   bool on;
   int err = 0;
-  ProfScope(int kernel, hipStream_t s, double work) : st(s), on(g_prof.kernel == kernel && kernel != KC_NONE) {
+  ProfScope(int kernel, hipStream_t s, double work, double bytes)
+      : st(s), on(g_prof.kernel == kernel && kernel != KC_NONE) {
     if (!on) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
@@ -1007,6 +1009,7 @@ struct ProfScope {
     hipEventRecord(g_prof.ev[g_prof.used], st);
     g_prof.launches += 1;
     g_prof.work += work;
+    g_prof.bytes += bytes;
   }
   ~ProfScope() {
     if (!on) return;
@@ -1073,10 +1076,11 @@ int profile_begin(int kernel) {
   g_prof.used = 0;
   g_prof.launches = 0;
   g_prof.work = 0.0;
+  g_prof.bytes = 0.0;
   return 0;
 }
 
-int profile_end(double* ms, int64_t* launches, double* work) {
+int profile_end(double* ms, int64_t* launches, double* work, double* bytes) {
   double tot = 0.0;
   for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
     hipError_t e = hipEventSynchronize(g_prof.ev[i + 1]);
@@ -1089,6 +1093,7 @@ int profile_end(double* ms, int64_t* launches, double* work) {
   *ms = tot;
   *launches = g_prof.launches;
   *work = g_prof.work;
+  *bytes = g_prof.bytes;
   g_prof.kernel = KC_NONE;
   g_prof.used = 0;
   return 0;
@@ -1137,7 +1142,8 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
   PXS_CHECK_LAUNCH();
   {
     // bytes: H, S, offsets read once per shift block; one element written per entry and shift
-    ProfScope ps(KC_ASSEMBLE, st, (double)S.nnz_lower * (24.0 + (CPLX ? 16.0 : 8.0) * nshift));
+    const double ab = (double)S.nnz_lower * (24.0 + (CPLX ? 16.0 : 8.0) * nshift);
+    ProfScope ps(KC_ASSEMBLE, st, ab, ab);
     hipLaunchKernelGGL(k_assemble<CPLX>, dim3(blocks_for(S.nnz_lower, 2048), nshift), dim3(NT), 0, st,
                        (double*)L, S.nnzL_store, H, Sv, eoff, S.nnz_lower, (const double*)(w + WK_SHIFTS));
   }
@@ -1145,6 +1151,7 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
   Common c = make_common(S, L, work);
   const int TR = S.tile_rows;
   const double fm = CPLX ? 8.0 : 2.0;   // flops per multiply-add
+  const double eb = CPLX ? 16.0 : 8.0;  // bytes per element
   const size_t np = S.panels.size();
   for (size_t ip = 0; ip < np; ++ip) {
     const Panel& P = S.panels[ip];
@@ -1152,19 +1159,22 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
     if (k.p0 > 0) {
       // left-looking: the panel's rows receive the earlier columns of its supernode
       const int nrows = k.ld - k.p0;
-      ProfScope ps(KC_UPDATE, st, fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0);
+      ProfScope ps(KC_UPDATE, st, fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0,
+                   eb * nshift * ((double)nrows * k.p0 + 2.0 * nrows * k.wp));
       if (TR == 64)
         hipLaunchKernelGGL((k_int_update<CPLX, 64>), dim3((nrows + 63) / 64, nshift), dim3(NT), 0, st, c, k);
       else
         hipLaunchKernelGGL((k_int_update<CPLX, 128>), dim3((nrows + 127) / 128, nshift), dim3(NT), 0, st, c, k);
     }
     {
-      ProfScope ps(KC_DIAG, st, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0);
+      ProfScope ps(KC_DIAG, st, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0,
+                   eb * nshift * (double)k.wp * (k.wp + 1));
       hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NTD), 0, st, c, k);
     }
     if (k.nb > 0) {
       const int nt = (k.nb + TR - 1) / TR;
-      ProfScope ps(KC_TRSM, st, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
+      ProfScope ps(KC_TRSM, st, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0,
+                   eb * nshift * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)));
       if (TR == 64)
         hipLaunchKernelGGL((k_trsm<CPLX, 64>), dim3(nt, nshift), dim3(NT), 0, st, c, k);
       else
@@ -1180,7 +1190,8 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
       u.wp = w;
       u.nb = below;
       const int ntj = (below + TM - 1) / TM, nti = (below + TR - 1) / TR;
-      ProfScope ps(KC_UPDATE, st, fm * nshift * (double)below * (below + 1) / 2.0 * w);
+      ProfScope ps(KC_UPDATE, st, fm * nshift * (double)below * (below + 1) / 2.0 * w,
+                   eb * nshift * ((double)below * w + (double)below * (below + 1)));
       if (TR == 64)
         hipLaunchKernelGGL((k_update<CPLX, 64>), dim3(ntj * nti, nshift), dim3(NT), 0, st, c, u);
       else
@@ -1317,21 +1328,25 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
         if (k.nb > 0) {
           const int nt = (k.nb + TR - 1) / TR;
           {
-            ProfScope ps(KC_LHAT, sj, 8.0 * nsh * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
+            ProfScope ps(KC_LHAT, sj, 8.0 * nsh * (double)k.nb * k.wp * (k.wp + 1) / 2.0,
+                         16.0 * nsh * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)));
             if (TR == 64)
               hipLaunchKernelGGL(k_lhat<64>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
             else
               hipLaunchKernelGGL(k_lhat<128>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
           }
           {
-            ProfScope ps(KC_SELINV_OFF, sj, 8.0 * nsh * (double)k.nb * k.nb * k.wp);
+            // bytes: Z_BB (one triangle), L-hat read, Z_Bp written
+            ProfScope ps(KC_SELINV_OFF, sj, 8.0 * nsh * (double)k.nb * k.nb * k.wp,
+                         16.0 * nsh * (0.5 * k.nb * (k.nb + 1) + 2.0 * k.nb * k.wp));
             if (TR == 64)
               hipLaunchKernelGGL(k_selinv_off<64>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
             else
               hipLaunchKernelGGL(k_selinv_off<128>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
           }
           {
-            ProfScope ps(KC_SELINV_DIAG, sj, 8.0 * nsh * (double)k.nb * k.wp * k.wp);
+            ProfScope ps(KC_SELINV_DIAG, sj, 8.0 * nsh * (double)k.nb * k.wp * k.wp,
+                         16.0 * nsh * (2.0 * k.nb * k.wp + (double)k.wp * k.wp));
             hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, nsh), dim3(NT), 0, sj, c, k);
           }
         }
@@ -1364,7 +1379,8 @@ int run_pole_sum_kernels(const Symbolic& S, int nshift, const void* L, void* wor
   const char* m = (const char*)S.dmaps;
   const int nb = blocks_for(S.nnz_lower, POLESUM_BLOCKS);
   // bytes: one complex per entry and shift, offsets, flags, H, S, nsets outputs
-  ProfScope ps(KC_POLESUM, st, (double)S.nnz_lower * (16.0 * nshift + 28.0 + 8.0 * nsets));
+  const double ab = (double)S.nnz_lower * (16.0 * nshift + 28.0 + 8.0 * nsets);
+  ProfScope ps(KC_POLESUM, st, ab, ab);
   hipLaunchKernelGGL(k_pole_sum, dim3(nb), dim3(NT), 0, st, (const double*)L, S.nnzL_store, nshift,
                      (const double*)(w + WK_WEIGHTS), nsets, (const int64_t*)(m + S.o_entry_off),
                      (const int32_t*)(m + S.o_entry_diag), S.nnz_lower, H, Sv, out,
