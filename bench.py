@@ -308,7 +308,10 @@ def main():
         from paper_1405_0194_amd import tune
         a = tune.tuned_analysis(s, lattice.CONFIG_POLES[cfg])
     t_an = time.perf_counter() - t_an
+    t_bind = time.perf_counter()
     a.bind()
+    torch.cuda.synchronize()
+    t_bind = time.perf_counter() - t_bind
     H = torch.from_numpy(s.hval).to(dev)
     S = torch.from_numpy(s.sval).to(dev)
     L, W = a.buffers(P)
@@ -320,11 +323,14 @@ def main():
     def step():
         return B.density_matrix(a, H, S, beta, dE, mu, P, nsets=2, L=L, work=W)
 
+    first_step = None
     for i in range(args.warmup):
         t = time.perf_counter()
         step()
         torch.cuda.synchronize()
-        print(f"# warmup {i}: {time.perf_counter() - t:.3f}s", file=sys.stderr, flush=True)
+        dt = time.perf_counter() - t
+        first_step = dt if first_step is None else first_step
+        print(f"# warmup {i}: {dt:.3f}s", file=sys.stderr, flush=True)
 
     B.profile_begin(args.profile_kernel)
     lat = []
@@ -355,6 +361,15 @@ def main():
     phases = {"assemble_factor_ms": e[0].elapsed_time(e[1]), "selinv_ms": e[1].elapsed_time(e[2]),
               "pole_sum_ms": e[2].elapsed_time(e[3])}
 
+    # achieved HBM rate of the memory-bound kernels (assembly, pole sum, Z_CC
+    # gather), one untimed step each
+    hbm = {}
+    for kname in ("assemble", "pole_sum", "gather"):
+        B.profile_begin(kname)
+        step()
+        hms, hl, hw = B.profile_end()
+        hbm[kname + "_GBps"] = round(hw / (hms / 1e3) / 1e9, 1) if hms > 0 else None
+
     solves = P * args.steps
     value = solves / elapsed
     flops_shift = a.info["flops_factor"] + a.info["flops_selinv"]
@@ -384,6 +399,9 @@ def main():
         "latency_s": {"p50": round(float(np.percentile(lat_sorted, 50)), 4),
                       "p99": round(float(np.percentile(lat_sorted, 99)), 4)},
         "phases_ms": {k: round(v, 2) for k, v in phases.items()},
+        "hbm_GBps": hbm,
+        "cold_s": {"analyze": round(t_an, 3), "bind": round(t_bind, 3),
+                   "first_density_matrix": round(first_step, 3) if first_step is not None else None},
         "roofline": {"kernel": args.profile_kernel, "bound": "mfma", "achieved": round(achieved, 3),
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4),

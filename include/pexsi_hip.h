@@ -233,11 +233,11 @@ void pxs_plan_free(pxs_plan plan);
  * selected kernel class is bracketed by HIP events on its launch stream.
  * kernel: 1 factor update, 2 SelInv off-diagonal product, 3 panel TRSM,
  *         4 SelInv diagonal-block product, 5 L-hat product, 6 diagonal-block
- *         LDL^T, 7 assembly, 8 pole sum.
+ *         LDL^T, 7 assembly, 8 pole sum, 9 SelInv gather of Z_CC.
  * pxs_profile_end synchronises those events and returns the summed kernel
  * time (ms), the number of launches, their algorithmic flops (complex
  * multiply-add = 8 flops, on the stored supernodal structure, no tile
- * padding; for kernels 7 and 8 their algorithmic HBM bytes instead) and, in
+ * padding; for kernels 7, 8 and 9 their algorithmic HBM bytes instead) and, in
  * `bytes` (nullable), their algorithmic HBM bytes: every operand read once
  * and every result written once.
  * Process-wide state; not thread safe.  PXS_ESTATE if no profile is open. */

@@ -401,7 +401,7 @@ def density_matrix(analysis: Analysis, H, S, beta, dE, mu, P, nsets=2, L=None, w
 
 
 KERNELS = {"update": 1, "selinv_off": 2, "trsm": 3, "selinv_diag": 4, "lhat": 5, "diag": 6,
-           "assemble": 7, "pole_sum": 8}
+           "assemble": 7, "pole_sum": 8, "gather": 9}
 
 
 def profile_begin(kernel: str):

@@ -436,7 +436,7 @@ void pxs_plan_free(pxs_plan plan) {
 }
 
 pxs_status pxs_profile_begin(int32_t kernel) {
-  if (kernel < 1 || kernel > 8) return PXS_EINVAL;
+  if (kernel < 1 || kernel > 9) return PXS_EINVAL;
   pxs::profile_begin(kernel);
   return PXS_OK;
 }
@@ -445,6 +445,10 @@ pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work, do
   if (!total_ms || !launches || !work) return PXS_EINVAL;
   double b = 0.0;
   int e = pxs::profile_end(total_ms, launches, work, &b);
+  if (e == -1) {
+    g_last_error = "pxs_profile_end: no profile is open";
+    return PXS_ESTATE;
+  }
   if (bytes) *bytes = b;
   if (e != 0) return hip_fail(e);
   return PXS_OK;

@@ -1081,6 +1081,7 @@ int profile_begin(int kernel) {
 }
 
 int profile_end(double* ms, int64_t* launches, double* work, double* bytes) {
+  if (g_prof.kernel == KC_NONE) return -1;   // no profile open
   double tot = 0.0;
   for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
     hipError_t e = hipEventSynchronize(g_prof.ev[i + 1]);
@@ -1320,6 +1321,9 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
       g.sh0 = sh0;
       if (g.c > 0) {
         const int nt = (g.c + TM - 1) / TM;
+        // bytes: the lower triangle of Z_CC read from the ancestors and written to G, relative positions
+        const double gb = (32.0 * nsh + 4.0) * 0.5 * g.c * (g.c + 1);
+        ProfScope ps(KC_GATHER, sj, gb, gb);
         hipLaunchKernelGGL(k_gather_cc, dim3(nt * (nt + 1) / 2, nsh), dim3(NT), 0, sj, c, g);
       }
       for (int ip = last; ip >= first; --ip) {

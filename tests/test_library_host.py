@@ -180,3 +180,17 @@ def test_analyze_rejects_bad_blocks():
         B.Analysis(3, colptr, rows, blkptr=np.array([0, 2, 2, 3]))
     with pytest.raises(B.PxsError):
         B.Analysis(3, colptr, rows, blkptr=np.array([0, 1, 4]))
+
+
+def test_profile_rejects_bad_class_and_unopened_profile():
+    lib = B.load()
+    assert lib.pxs_profile_begin(0) == B.PXS_EINVAL
+    assert lib.pxs_profile_begin(10) == B.PXS_EINVAL
+    with pytest.raises(B.PxsError):
+        B.profile_end()
+    # an open profile with no launches closes cleanly (no device work)
+    B.profile_begin("gather")
+    ms, n, w, b = B.profile_end(with_bytes=True)
+    assert (ms, n, w, b) == (0.0, 0, 0.0, 0.0)
+    with pytest.raises(B.PxsError):
+        B.profile_end()
