@@ -1,0 +1,50 @@
+"""Host logic of the chemical-potential search (no GPU): the library-side
+bracketing and integration by parts agree with the oracle's independent
+implementation when both are given the same counts."""
+import numpy as np
+import pytest
+
+from oracle import chempot as oc
+from paper_1405_0194_amd import chempot as pc
+
+BETA = 1052.58
+
+
+@pytest.mark.parametrize("beta", [BETA, 40.0, 1e9])
+def test_integration_by_parts_matches_oracle(beta):
+    rng = np.random.default_rng(5)
+    eps = np.sort(rng.uniform(-1, 1, 16))
+    ninf = 2.0 * np.cumsum(rng.integers(0, 5, 16))
+    mus = np.linspace(-1.3, 1.3, 53)
+    got = pc.n_beta_from_counts(eps, ninf, mus, beta)
+    for m, g in zip(mus, got):
+        assert abs(g - oc.n_beta_from_samples(eps, ninf, m, beta)) <= 1e-11 * max(1.0, ninf[-1])
+
+
+@pytest.mark.parametrize("case", ["gapped", "dense", "widen"])
+def test_bracket_matches_oracle(case):
+    rng = np.random.default_rng(6)
+    if case == "gapped":
+        ev = np.sort(np.concatenate([rng.uniform(-0.9, -0.15, 30), rng.uniform(0.25, 0.9, 30)]))
+        Ne, lo, hi = 60.0, -1.0, 1.0
+    elif case == "dense":
+        ev = np.sort(rng.uniform(-0.9, 0.9, 200))
+        Ne, lo, hi = 2.0 * 123 + 1.0, -1.0, 1.0
+    else:
+        ev = np.sort(rng.uniform(-0.9, 0.9, 100))
+        Ne, lo, hi = 150.0, -0.9, -0.6
+    cnt = oc.counts_from_eigenvalues(ev)
+    br = pc.bracket_from_counts(cnt, Ne, lo, hi, BETA, Q=16, dN=0.1, rounds=3)
+    olo, ohi, omu, _ = oc.bracket(cnt, Ne, lo, hi, BETA, Q=16, dN=0.1, rounds=3)
+    scale = 1e-12 * (hi - lo)
+    assert abs(br.lo - olo) <= scale and abs(br.hi - ohi) <= scale and abs(br.mu - omu) <= scale
+    n_lo = 2 * cnt(np.array([br.lo]))[0]
+    n_hi = 2 * cnt(np.array([br.hi]))[0]
+    assert n_lo <= Ne <= n_hi
+
+
+def test_bracket_rejects_bad_interval():
+    with pytest.raises(ValueError):
+        pc.bracket_from_counts(lambda e: np.zeros(len(e)), 1.0, 1.0, 0.0, BETA)
+    with pytest.raises(RuntimeError):
+        pc.bracket_from_counts(lambda e: np.zeros(len(e), dtype=int), 10.0, -1.0, 1.0, BETA, max_expand=3)
