@@ -156,56 +156,79 @@ class NewtonResult:
     traces: object = None       # (4, 2): Tr(G S), Tr(G H) per set
 
 
-def newton_mu(analysis, H, S, Ne, mu0, lo, hi, beta, P, spectrum=(-1.0, 1.0), tol_ne=1e-8, maxit=30,
-              L=None, work=None, stream=None):
-    """Safeguarded Newton for Tr[Gamma_P(mu) S] = Ne inside [lo, hi].
-    spectrum bounds the pencil's eigenvalues; Delta E = max |bound - mu|."""
-    if L is None or work is None:
-        L, work = analysis.buffers(P, device=H.device)
+def newton_from(evaluate, Ne, mu0, lo, hi, spectrum=(-1.0, 1.0), tol_ne=1e-8, maxit=30):
+    """Safeguarded Newton for N(mu) = Ne inside [lo, hi]; evaluate(mu)
+    returns (N, N', payload).  Returns (mu, N, N', iterations, lo, hi,
+    history, payload of the last evaluation)."""
     hist = []
     mu = float(mu0)
     if not lo <= mu <= hi:
         mu = 0.5 * (lo + hi)
-    # an end of [lo, hi] is confirmed once N has been evaluated there; a step
-    # past an unconfirmed end widens the interval (mu left the bracket), a
-    # step past a confirmed one is replaced by bisection.  Steps never leave
-    # the spectrum's range, outside which N is constant.
+    # an end of [lo, hi] is confirmed once N has been evaluated there.  While
+    # the root may lie past an unconfirmed end (mu left a reused bracket) that
+    # end is widened geometrically and probed; otherwise a step outside the
+    # interval is replaced by bisection.  Nothing leaves the spectrum's
+    # range, outside which N is constant.
     lo_ok = hi_ok = False
     smin = spectrum[0] - 1e-3 * (spectrum[1] - spectrum[0])
     smax = spectrum[1] + 1e-3 * (spectrum[1] - spectrum[0])
-    out = tr = None
+    grow = max(hi - lo, 1e-3 * (smax - smin))    # doubles with every widening
+    payload = None
     N = dN = float("nan")
     for it in range(1, maxit + 1):
+        N, dN, payload = evaluate(mu)
+        hist.append(dict(mu=mu, N=N, dN=dN))
+        if abs(N - Ne) <= tol_ne:
+            return mu, N, dN, it, lo, hi, hist, payload
+        if N < Ne:
+            lo, lo_ok = mu, True
+        else:
+            hi, hi_ok = mu, True
+        # Newton step; far from mu* the expansion of N' can be unreliable
+        # (even negative), so only a positive N' gives a step
+        step = mu - (N - Ne) / dN if dN > 0 else float("nan")
+        if np.isfinite(step):
+            step = min(max(step, smin), smax)
+        probe = None
+        if N < Ne and not hi_ok and not (np.isfinite(step) and step < hi):
+            # mu* may lie above the guessed upper end: widen it and probe it
+            hi = min(smax, hi + grow)
+            grow *= 2.0
+            probe = hi
+        elif N > Ne and not lo_ok and not (np.isfinite(step) and step > lo):
+            lo = max(smin, lo - grow)
+            grow *= 2.0
+            probe = lo
+        if probe is not None:
+            mu = probe
+        elif np.isfinite(step) and lo < step < hi:
+            mu = step
+        else:
+            mu = 0.5 * (lo + hi)
+        if lo_ok and hi_ok and hi - lo <= 4 * np.finfo(float).eps * max(1.0, abs(mu)):
+            break
+    return mu, N, dN, len(hist), lo, hi, hist, payload
+
+
+def newton_mu(analysis, H, S, Ne, mu0, lo, hi, beta, P, spectrum=(-1.0, 1.0), tol_ne=1e-8, maxit=30,
+              L=None, work=None, stream=None):
+    """Newton for Tr[Gamma_P(mu) S] = Ne; every iterate is one density
+    matrix (weight sets rho, E, F, d) on the device.  spectrum bounds the
+    pencil's eigenvalues; Delta E = max |bound - mu|."""
+    if L is None or work is None:
+        L, work = analysis.buffers(P, device=H.device)
+
+    def evaluate(mu):
         dE = max(abs(spectrum[0] - mu), abs(spectrum[1] - mu))
         out, tr, info, _, _ = B.density_matrix(analysis, H, S, beta, dE, mu, P, nsets=4, L=L, work=work,
                                                stream=stream)
         if np.any(info):
             raise B.PxsError("newton_mu", B.PXS_TINY_PIVOT, f"tiny pivot at mu={mu}")
-        N, dN = float(tr[0, 0]), float(tr[3, 0])
-        hist.append(dict(mu=mu, N=N, dN=dN))
-        if abs(N - Ne) <= tol_ne:
-            return NewtonResult(mu, N, dN, it, lo, hi, hist, out, tr)
-        if N < Ne:
-            lo, lo_ok = mu, True
-        else:
-            hi, hi_ok = mu, True
-        step = mu - (N - Ne) / dN if dN > 0 else float("nan")
-        if np.isfinite(step):
-            step = min(max(step, smin), smax)
-            if step >= hi and not hi_ok:
-                hi = step + (step - mu)
-            elif step <= lo and not lo_ok:
-                lo = step - (mu - step)
-        if np.isfinite(step) and lo < step < hi:
-            mu = step
-        elif not (lo_ok and hi_ok) and not np.isfinite(step):
-            # no usable derivative and one side unknown: move toward it
-            mu = hi if not hi_ok else lo
-        else:
-            mu = 0.5 * (lo + hi)
-        if lo_ok and hi_ok and hi - lo <= 4 * np.finfo(float).eps * max(1.0, abs(mu)):
-            break
-    return NewtonResult(mu, N, dN, len(hist), lo, hi, hist, out, tr)
+        return float(tr[0, 0]), float(tr[3, 0]), (out, tr)
+
+    mu, N, dN, it, lo, hi, hist, payload = newton_from(evaluate, Ne, mu0, lo, hi, spectrum, tol_ne, maxit)
+    out, tr = payload if payload is not None else (None, None)
+    return NewtonResult(mu, N, dN, it, lo, hi, hist, out, tr)
 
 
 def solve_mu(analysis, H, S, Ne, beta, P, lo=-1.0, hi=1.0, spectrum=(-1.0, 1.0), Q=16, dN=0.1, rounds=3,

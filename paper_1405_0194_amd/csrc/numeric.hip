@@ -215,43 +215,37 @@ __device__ __forceinline__ void commit(double* re, double* im, const cplx (&v)[X
   }
 }
 
+// Runtime choice of the staging order for operands whose memory order
+// changes from chunk to chunk (a symmetric operand read through one
+// triangle).  The flag is uniform across the workgroup; the two slot maps
+// are blended with selects, so fetch and commit stay branch-free and the
+// pipeline below remains one basic block per chunk.
+template <int ROWS>
+__device__ __forceinline__ void slot_sel(int j, bool fast, int& ii, int& kk) {
+  const int t = threadIdx.x;
+  const int ir = t % ROWS, kr = t / ROWS + (NT / ROWS) * j;
+  const int kf = t % KC, jf = t / KC + (NT / KC) * j;
+  ii = fast ? jf : ir;
+  kk = fast ? kf : kr;
+}
+
 template <int ROWS, int X, class Gt>
 __device__ __forceinline__ void fetch_rt(cplx (&v)[X], int k0, Gt get, bool fast) {
-  if (fast) fetch<ROWS, X, true>(v, k0, get);
-  else fetch<ROWS, X, false>(v, k0, get);
+#pragma unroll
+  for (int j = 0; j < X; ++j) {
+    int ii, kk;
+    slot_sel<ROWS>(j, fast, ii, kk);
+    v[j] = get(ii, k0 + kk);
+  }
 }
 template <bool CPLX, int ROWS, int X>
 __device__ __forceinline__ void commit_rt(double* re, double* im, const cplx (&v)[X], bool fast) {
-  if (fast) commit<CPLX, ROWS, X, true>(re, im, v);
-  else commit<CPLX, ROWS, X, false>(re, im, v);
-}
-
-// Software-pipelined K loop over [kb, ke): P += A[:, k] B[k, :].  ga(m, k)
-// and gb(n, k) return the operands (zero outside the matrices); bfast(k0)
-// picks the B staging order per chunk (uniform across the workgroup).
-template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF>
-__device__ __forceinline__ void gemm_pipe(Acc<CPLX, NTILE>& acc, Stage<CPLX, NTILE>& s, int kb, int ke,
-                                          GA ga, GB gb, BF bfast) {
-  using G = Geo<NTILE>;
-  cplx ra[G::XA], rb[G::XB];
-  bool fb = false;
-  if (kb < ke) {
-    fb = bfast(kb);
-    fetch<64, G::XA, AFAST>(ra, kb, ga);
-    fetch_rt<NTILE, G::XB>(rb, kb, gb, fb);
-  }
-  for (int k0 = kb; k0 < ke; k0 += KC) {
-    __syncthreads();
-    commit<CPLX, 64, G::XA, AFAST>(&s.a_re[0][0], &s.a_im[0][0], ra);
-    commit_rt<CPLX, NTILE, G::XB>(&s.b_re[0][0], &s.b_im[0][0], rb, fb);
-    __syncthreads();
-    const int k1 = k0 + KC;
-    if (k1 < ke) {
-      fb = bfast(k1);
-      fetch<64, G::XA, AFAST>(ra, k1, ga);
-      fetch_rt<NTILE, G::XB>(rb, k1, gb, fb);
-    }
-    mfma_chunk<CPLX, NTILE>(acc, s);
+#pragma unroll
+  for (int j = 0; j < X; ++j) {
+    int ii, kk;
+    slot_sel<ROWS>(j, fast, ii, kk);
+    re[kk * (ROWS + 1) + ii] = v[j].re;
+    if (CPLX) im[kk * (ROWS + 1) + ii] = v[j].im;
   }
 }
 
@@ -272,106 +266,59 @@ __device__ __forceinline__ void xcd_remap(int& x, int& y) {
   y = logical / nx;
 }
 
-// Double-buffered variant: the chunk in registers is committed to the other
-// LDS buffer right after the MFMAs of the current chunk are issued, so the
-// LDS writes and the next fetch overlap the matrix-core work and one barrier
-// per chunk suffices (it orders both "commit before use" and "use before
-// overwrite", since each buffer is rewritten one iteration after its use).
+// Double-buffered LDS (two stages) with a two-chunk-deep register
+// prefetch: two register sets alternate, so a chunk's global loads have two
+// chunks of matrix-core time to land, and one barrier per chunk orders both
+// "commit before use" and "use before overwrite" (each stage is rewritten
+// one chunk after its use).
+//   prologue: R0 <- c0, R1 <- c1, commit R0 -> buf0, R0 <- c2
+//   even c:   mfma(buf0); commit R1 (c+1) -> buf1; R1 <- c+3
+//   odd  c:   mfma(buf1); commit R0 (c+1) -> buf0; R0 <- c+3
+// Chunks past the end are fetched as the last chunk again (clamped index,
+// same memory, never used) and committed to the idle stage, so the loop body
+// has no data-dependent branches and the wait counts stay exact.
 template <bool CPLX, int NTILE>
 struct Stage2 {
   Stage<CPLX, NTILE> buf[2];
 };
 
+// K loop over [kb, ke): P += A[:, k] B[k, :].  ga(m, k) and gb(n, k) return
+// the operands (zero outside the matrices); bfast(k0) picks the B staging
+// order per chunk.
 template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF>
-__device__ __forceinline__ void gemm_pipe2(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NTILE>& s, int kb, int ke,
-                                           GA ga, GB gb, BF bfast) {
-  using G = Geo<NTILE>;
-  if (kb >= ke) return;
-  cplx ra[G::XA], rb[G::XB];
-  bool fb = bfast(kb);
-  fetch<64, G::XA, AFAST>(ra, kb, ga);
-  fetch_rt<NTILE, G::XB>(rb, kb, gb, fb);
-  commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra);
-  commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb, fb);
-  if (kb + KC < ke) {
-    fb = bfast(kb + KC);
-    fetch<64, G::XA, AFAST>(ra, kb + KC, ga);
-    fetch_rt<NTILE, G::XB>(rb, kb + KC, gb, fb);
-  }
-  __syncthreads();
-  int cur = 0;
-  for (int k0 = kb; k0 < ke; k0 += KC) {
-    mfma_chunk<CPLX, NTILE>(acc, s.buf[cur]);
-    if (k0 + KC < ke) {
-      Stage<CPLX, NTILE>& nb = s.buf[cur ^ 1];
-      commit<CPLX, 64, G::XA, AFAST>(&nb.a_re[0][0], &nb.a_im[0][0], ra);
-      commit_rt<CPLX, NTILE, G::XB>(&nb.b_re[0][0], &nb.b_im[0][0], rb, fb);
-      if (k0 + 2 * KC < ke) {
-        fb = bfast(k0 + 2 * KC);
-        fetch<64, G::XA, AFAST>(ra, k0 + 2 * KC, ga);
-        fetch_rt<NTILE, G::XB>(rb, k0 + 2 * KC, gb, fb);
-      }
-    }
-    __syncthreads();
-    cur ^= 1;
-  }
-}
-
-// Two-chunk-deep prefetch on top of the double-buffered LDS: two register
-// sets alternate (the loop is unrolled by two so both stay in registers),
-// so a chunk's global loads have two chunks of matrix-core time to land.
-//   prologue: R0 <- c0, R1 <- c1, commit R0 -> buf0, R0 <- c2
-//   even c:   mfma(buf0); commit R1 (c+1) -> buf1; R1 <- c+3
-//   odd  c:   mfma(buf1); commit R0 (c+1) -> buf0; R0 <- c+3
-// with one barrier after each step.
-template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF>
-__device__ __forceinline__ void gemm_pipe3(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NTILE>& s, int kb, int ke,
-                                           GA ga, GB gb, BF bfast) {
+__device__ __forceinline__ void gemm_pipe(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NTILE>& s, int kb, int ke,
+                                          GA ga, GB gb, BF bfast) {
   using G = Geo<NTILE>;
   if (kb >= ke) return;
   const int nc = (ke - kb + KC - 1) / KC;
+  auto kat = [&](int c) { return kb + min(c, nc - 1) * KC; };
   cplx ra0[G::XA], rb0[G::XB], ra1[G::XA], rb1[G::XB];
-  bool fb0 = bfast(kb), fb1 = false;
-  fetch<64, G::XA, AFAST>(ra0, kb, ga);
-  fetch_rt<NTILE, G::XB>(rb0, kb, gb, fb0);
-  if (nc > 1) {
-    fb1 = bfast(kb + KC);
-    fetch<64, G::XA, AFAST>(ra1, kb + KC, ga);
-    fetch_rt<NTILE, G::XB>(rb1, kb + KC, gb, fb1);
-  }
+  bool fb0 = bfast(kat(0)), fb1 = bfast(kat(1));
+  fetch<64, G::XA, AFAST>(ra0, kat(0), ga);
+  fetch_rt<NTILE, G::XB>(rb0, kat(0), gb, fb0);
+  fetch<64, G::XA, AFAST>(ra1, kat(1), ga);
+  fetch_rt<NTILE, G::XB>(rb1, kat(1), gb, fb1);
   commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra0);
   commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb0, fb0);
-  if (nc > 2) {
-    fb0 = bfast(kb + 2 * KC);
-    fetch<64, G::XA, AFAST>(ra0, kb + 2 * KC, ga);
-    fetch_rt<NTILE, G::XB>(rb0, kb + 2 * KC, gb, fb0);
-  }
+  fb0 = bfast(kat(2));
+  fetch<64, G::XA, AFAST>(ra0, kat(2), ga);
+  fetch_rt<NTILE, G::XB>(rb0, kat(2), gb, fb0);
   __syncthreads();
   for (int c = 0; c < nc; c += 2) {
     mfma_chunk<CPLX, NTILE>(acc, s.buf[0]);
-    if (c + 1 < nc) {
-      commit<CPLX, 64, G::XA, AFAST>(&s.buf[1].a_re[0][0], &s.buf[1].a_im[0][0], ra1);
-      commit_rt<CPLX, NTILE, G::XB>(&s.buf[1].b_re[0][0], &s.buf[1].b_im[0][0], rb1, fb1);
-      if (c + 3 < nc) {
-        const int k3 = kb + (c + 3) * KC;
-        fb1 = bfast(k3);
-        fetch<64, G::XA, AFAST>(ra1, k3, ga);
-        fetch_rt<NTILE, G::XB>(rb1, k3, gb, fb1);
-      }
-    }
+    commit<CPLX, 64, G::XA, AFAST>(&s.buf[1].a_re[0][0], &s.buf[1].a_im[0][0], ra1);
+    commit_rt<CPLX, NTILE, G::XB>(&s.buf[1].b_re[0][0], &s.buf[1].b_im[0][0], rb1, fb1);
+    fb1 = bfast(kat(c + 3));
+    fetch<64, G::XA, AFAST>(ra1, kat(c + 3), ga);
+    fetch_rt<NTILE, G::XB>(rb1, kat(c + 3), gb, fb1);
     __syncthreads();
     if (c + 1 >= nc) break;
     mfma_chunk<CPLX, NTILE>(acc, s.buf[1]);
-    if (c + 2 < nc) {
-      commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra0);
-      commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb0, fb0);
-      if (c + 4 < nc) {
-        const int k4 = kb + (c + 4) * KC;
-        fb0 = bfast(k4);
-        fetch<64, G::XA, AFAST>(ra0, k4, ga);
-        fetch_rt<NTILE, G::XB>(rb0, k4, gb, fb0);
-      }
-    }
+    commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra0);
+    commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb0, fb0);
+    fb0 = bfast(kat(c + 4));
+    fetch<64, G::XA, AFAST>(ra0, kat(c + 4), ga);
+    fetch_rt<NTILE, G::XB>(rb0, kat(c + 4), gb, fb0);
     __syncthreads();
   }
 }
@@ -591,7 +538,7 @@ __global__ void PXS_LB(TN) k_trsm(Common c, PanelK p) {
   }
   Acc<CPLX, TN> acc;
   acc.zero();
-  gemm_pipe3<CPLX, TN, false>(
+  gemm_pipe<CPLX, TN, false>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[c][k]: column k of the diagonal block
         if (m >= p.wp || kg >= p.wp || m < kg) return cplx{0.0, 0.0};
@@ -625,7 +572,7 @@ __global__ void PXS_LB(TN) k_int_update(Common c, PanelK p) {
   const int64_t cbase = p.off + p.p0;        // element (row p0, column 0)
   Acc<CPLX, TN> acc;
   acc.zero();
-  gemm_pipe3<CPLX, TN, false>(
+  gemm_pipe<CPLX, TN, false>(
       acc, s, 0, p.p0,
       [&](int m, int kg) -> cplx {   // d_k L[p0 + c][k]
         if (m >= p.wp || kg >= p.p0) return cplx{0.0, 0.0};
@@ -682,7 +629,7 @@ __global__ void PXS_LB(TN) k_update(Common c, PanelK p) {
   const int kb = p.p0, ke = p.p0 + p.wp;
   Acc<CPLX, TN> acc;
   acc.zero();
-  gemm_pipe3<CPLX, TN, false>(
+  gemm_pipe<CPLX, TN, false>(
       acc, s, kb, ke,
       [&](int m, int kg) -> cplx {
         const int jg = j0 + m;
@@ -732,7 +679,7 @@ __global__ void PXS_LB(TN) k_lhat(Common c, PanelK p) {
   const int64_t rbase = dbase + p.wp;
   Acc<true, TN> acc;
   acc.zero();
-  gemm_pipe3<true, TN, true>(
+  gemm_pipe<true, TN, true>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[k][c]: column c of the diagonal block, rows k
         if (m >= p.wp || kg >= p.wp || kg < m) return cplx{0.0, 0.0};
@@ -768,7 +715,7 @@ __global__ void PXS_LB(TN) k_selinv_off(Common c, PanelK p) {
   const int base = p.p0 + p.wp;
   Acc<true, TN> acc;
   acc.zero();
-  gemm_pipe3<true, TN, true>(
+  gemm_pipe<true, TN, true>(
       acc, s, 0, p.nb,
       [&](int m, int kg) -> cplx {
         if (m >= p.wp || kg >= p.nb) return cplx{0.0, 0.0};
@@ -843,7 +790,7 @@ __global__ void PXS_LB(64) k_selinv_diag_partial(Common c, PanelK p) {
   const int kb = sp * 512, ke = min(p.nb, kb + 512);
   Acc<true, TM> acc;
   acc.zero();
-  gemm_pipe3<true, TM, true>(
+  gemm_pipe<true, TM, true>(
       acc, s, kb, ke,
       [&](int m, int kg) -> cplx {
         if (m >= p.wp || kg >= ke) return cplx{0.0, 0.0};

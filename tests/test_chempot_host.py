@@ -48,3 +48,22 @@ def test_bracket_rejects_bad_interval():
         pc.bracket_from_counts(lambda e: np.zeros(len(e)), 1.0, 1.0, 0.0, BETA)
     with pytest.raises(RuntimeError):
         pc.bracket_from_counts(lambda e: np.zeros(len(e), dtype=int), 10.0, -1.0, 1.0, BETA, max_expand=3)
+
+
+def _pole_evaluator(ev, P, spec):
+    return lambda mu: (*oc.n_pole(ev, mu, BETA, P, spec), None)
+
+
+@pytest.mark.parametrize("mu0,lo,hi", [(0.0, -0.02, 0.02),      # root far above a reused bracket
+                                       (0.6, 0.55, 0.65),       # root far below it
+                                       (0.15, -1.0, 1.0)])      # wide bracket
+def test_newton_converges_and_recovers_outside_bracket(mu0, lo, hi):
+    rng = np.random.default_rng(7)
+    ev = np.sort(rng.uniform(-0.19, 0.19, 120)) * 0.8 + 0.15
+    Ne = 120.37
+    spec = (-1.0, 1.0)
+    mu, N, dN, it, *_ = pc.newton_from(_pole_evaluator(ev, 40, spec), Ne, mu0, lo, hi, spec, tol_ne=1e-8,
+                                       maxit=60)
+    mu_star = oc.mu_exact(ev, Ne, BETA, 40, spec, -0.99, 0.99)
+    assert abs(N - Ne) <= 1e-8
+    assert abs(mu - mu_star) <= 1e-8 / dN + 1e-12
