@@ -361,6 +361,23 @@ def main():
     phases = {"assemble_factor_ms": e[0].elapsed_time(e[1]), "selinv_ms": e[1].elapsed_time(e[2]),
               "pole_sum_ms": e[2].elapsed_time(e[3])}
 
+    # the dominant kernel once more with every launch alone on the device
+    # (SelInv on one stream): launch durations not stretched by concurrency
+    iso = None
+    if args.profile_kernel in ("selinv_off", "selinv_diag", "lhat", "gather"):
+        a1 = B.Analysis.from_system(s, **{**a.options, "selinv_streams": 1}).bind()
+        W1 = W if a1.workspace_size(P) <= W.numel() else None
+        L1, W1 = (L, W1) if W1 is not None else a1.buffers(P)
+        B.profile_begin(args.profile_kernel)
+        B.density_matrix(a1, H, S, beta, dE, mu, P, nsets=2, L=L1, work=W1)
+        ims, il, iw = B.profile_end()
+        if il:
+            iavg = ims / il
+            iach = (iw / il) / (iavg / 1e3) / 1e12
+            iso = {"achieved": round(iach, 3), "frac": round(iach / PEAK_FP64_TFLOPS, 4),
+                   "avg_launch_ms": round(iavg, 4), "launches": il}
+        del a1
+
     # achieved HBM rate of the memory-bound kernels (assembly, pole sum, Z_CC
     # gather), one untimed step each
     hbm = {}
@@ -407,7 +424,8 @@ def main():
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                      "avg_launch_ms": round(avg_ms, 4), "launches": klaunch,
                      "traffic": traffic,
-                     "algorithmic_bytes_per_launch": round(kbytes / max(klaunch, 1))},
+                     "algorithmic_bytes_per_launch": round(kbytes / max(klaunch, 1)),
+                     "isolated": iso},
     }
     if args.profile_kernel in ("assemble", "pole_sum"):
         gbs = (kwork / max(klaunch, 1)) / (avg_ms / 1e3) / 1e9 if klaunch else 0.0

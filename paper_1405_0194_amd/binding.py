@@ -159,6 +159,9 @@ class Analysis:
         self.n = int(n)
         colptr = np.ascontiguousarray(colptr, dtype=np.int64)
         rowind = np.ascontiguousarray(rowind, dtype=np.int32)
+        self.options = dict(ordering=ordering, leaf_cols=leaf_cols, panel_width=panel_width,
+                            pivot_tol=pivot_tol, selinv_chunk=selinv_chunk, tile_rows=tile_rows,
+                            selinv_streams=selinv_streams)
         opt = Options(ordering, leaf_cols, panel_width, selinv_chunk, pivot_tol, tile_rows, selinv_streams)
         h = _P()
         nblk = 0
