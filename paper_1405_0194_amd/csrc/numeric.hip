@@ -29,6 +29,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cstdint>
 #include <cstdio>
 #include <vector>
@@ -118,9 +119,16 @@ struct Stage {
   double a_im[CPLX ? KC : 1][LDP];
   double b_re[KC][NTILE + 1];
   double b_im[CPLX ? KC : 1][NTILE + 1];
+  double d_re[KC];                 // per-k scale of the A operand (optional)
+  double d_im[CPLX ? KC : 1];
 };
 
-template <bool CPLX, int NTILE>
+// No per-k scaling of the A operand.
+struct NoScale {};
+
+// SCALE: A[m][k] is multiplied by the chunk's d_k (staged with the chunk)
+// as it is read for the matrix cores.
+template <bool CPLX, int NTILE, bool SCALE = false>
 __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CPLX, NTILE>& s) {
   using G = Geo<NTILE>;
   const int lane = threadIdx.x & 63;
@@ -135,6 +143,21 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CP
     for (int t = 0; t < G::BM; ++t) {
       ar[t] = s.a_re[k][wm + t * 16 + li];
       if (CPLX) ai[t] = s.a_im[k][wm + t * 16 + li];
+    }
+    if (SCALE) {
+      const double dr = s.d_re[k];
+      if (CPLX) {
+        const double di = s.d_im[k];
+#pragma unroll
+        for (int t = 0; t < G::BM; ++t) {
+          const cplx v = cmul(cplx{dr, di}, cplx{ar[t], ai[t]});
+          ar[t] = v.re;
+          ai[t] = v.im;
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < G::BM; ++t) ar[t] *= dr;
+      }
     }
 #pragma unroll
     for (int t = 0; t < G::BN; ++t) {
@@ -284,41 +307,67 @@ struct Stage2 {
 
 // K loop over [kb, ke): P += A[:, k] B[k, :].  ga(m, k) and gb(n, k) return
 // the operands (zero outside the matrices); bfast(k0) picks the B staging
-// order per chunk.
-template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF>
+// order per chunk.  gd(k), unless NoScale, returns a factor d_k applied to
+// column k of A on its way to the matrix cores (one load per k and chunk
+// instead of one per element); it must accept any k of the last chunk.
+template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF, class GD = NoScale>
 __device__ __forceinline__ void gemm_pipe(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NTILE>& s, int kb, int ke,
-                                          GA ga, GB gb, BF bfast) {
+                                          GA ga, GB gb, BF bfast, GD gd = GD()) {
   using G = Geo<NTILE>;
+  constexpr bool SC = !std::is_same<GD, NoScale>::value;
   if (kb >= ke) return;
   const int nc = (ke - kb + KC - 1) / KC;
   auto kat = [&](int c) { return kb + min(c, nc - 1) * KC; };
+  const int t = threadIdx.x;
+  auto dfetch = [&](cplx& r, int k0) {
+    if constexpr (SC) {
+      if (t < KC) r = gd(k0 + t);
+    }
+  };
+  auto dcommit = [&](Stage<CPLX, NTILE>& st, const cplx& r) {
+    if constexpr (SC) {
+      if (t < KC) {
+        st.d_re[t] = r.re;
+        if (CPLX) st.d_im[t] = r.im;
+      }
+    }
+  };
   cplx ra0[G::XA], rb0[G::XB], ra1[G::XA], rb1[G::XB];
+  cplx rd0{1.0, 0.0}, rd1{1.0, 0.0};
   bool fb0 = bfast(kat(0)), fb1 = bfast(kat(1));
   fetch<64, G::XA, AFAST>(ra0, kat(0), ga);
   fetch_rt<NTILE, G::XB>(rb0, kat(0), gb, fb0);
+  dfetch(rd0, kat(0));
   fetch<64, G::XA, AFAST>(ra1, kat(1), ga);
   fetch_rt<NTILE, G::XB>(rb1, kat(1), gb, fb1);
+  dfetch(rd1, kat(1));
   commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra0);
   commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb0, fb0);
+  dcommit(s.buf[0], rd0);
   fb0 = bfast(kat(2));
   fetch<64, G::XA, AFAST>(ra0, kat(2), ga);
   fetch_rt<NTILE, G::XB>(rb0, kat(2), gb, fb0);
+  dfetch(rd0, kat(2));
   __syncthreads();
   for (int c = 0; c < nc; c += 2) {
-    mfma_chunk<CPLX, NTILE>(acc, s.buf[0]);
+    mfma_chunk<CPLX, NTILE, SC>(acc, s.buf[0]);
     commit<CPLX, 64, G::XA, AFAST>(&s.buf[1].a_re[0][0], &s.buf[1].a_im[0][0], ra1);
     commit_rt<CPLX, NTILE, G::XB>(&s.buf[1].b_re[0][0], &s.buf[1].b_im[0][0], rb1, fb1);
+    dcommit(s.buf[1], rd1);
     fb1 = bfast(kat(c + 3));
     fetch<64, G::XA, AFAST>(ra1, kat(c + 3), ga);
     fetch_rt<NTILE, G::XB>(rb1, kat(c + 3), gb, fb1);
+    dfetch(rd1, kat(c + 3));
     __syncthreads();
     if (c + 1 >= nc) break;
-    mfma_chunk<CPLX, NTILE>(acc, s.buf[1]);
+    mfma_chunk<CPLX, NTILE, SC>(acc, s.buf[1]);
     commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra0);
     commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb0, fb0);
+    dcommit(s.buf[0], rd0);
     fb0 = bfast(kat(c + 4));
     fetch<64, G::XA, AFAST>(ra0, kat(c + 4), ga);
     fetch_rt<NTILE, G::XB>(rb0, kat(c + 4), gb, fb0);
+    dfetch(rd0, kat(c + 4));
     __syncthreads();
   }
 }
@@ -574,17 +623,20 @@ __global__ void PXS_LB(TN) k_int_update(Common c, PanelK p) {
   acc.zero();
   gemm_pipe<CPLX, TN, false>(
       acc, s, 0, p.p0,
-      [&](int m, int kg) -> cplx {   // d_k L[p0 + c][k]
+      [&](int m, int kg) -> cplx {   // L[p0 + c][k] (times d_k on the way to the MFMAs)
         if (m >= p.wp || kg >= p.p0) return cplx{0.0, 0.0};
-        const cplx d = ld_elem<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg);
-        return cmul(d, ld_elem<CPLX>(Ls, cbase + (int64_t)kg * p.ld + m));
+        return ld_elem<CPLX>(Ls, cbase + (int64_t)kg * p.ld + m);
       },
       [&](int n, int kg) -> cplx {   // L[p0 + r][k]
         const int rg = r0 + n;
         if (kg >= p.p0 || rg >= nrows) return cplx{0.0, 0.0};
         return ld_elem<CPLX>(Ls, cbase + (int64_t)kg * p.ld + rg);
       },
-      RowsFast());
+      RowsFast(),
+      [&](int kg) -> cplx {          // d_k
+        if (kg >= p.p0) return cplx{0.0, 0.0};
+        return ld_elem<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg);
+      });
   acc_foreach<CPLX, TN>(acc, [&](int m, int n, cplx v) {
     const int rg = r0 + n;
     if (m < p.wp && rg < nrows && rg >= m) {
@@ -631,18 +683,21 @@ __global__ void PXS_LB(TN) k_update(Common c, PanelK p) {
   acc.zero();
   gemm_pipe<CPLX, TN, false>(
       acc, s, kb, ke,
-      [&](int m, int kg) -> cplx {
+      [&](int m, int kg) -> cplx {   // L[j][k] (times d_k on the way to the MFMAs)
         const int jg = j0 + m;
         if (kg >= ke || jg >= p.nb) return cplx{0.0, 0.0};
-        const cplx d = ld_elem<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg);
-        return cmul(d, ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + jg));
+        return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + jg);
       },
       [&](int n, int kg) -> cplx {
         const int ig = i0 + n;
         if (kg >= ke || ig >= p.nb) return cplx{0.0, 0.0};
         return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
       },
-      RowsFast());
+      RowsFast(),
+      [&](int kg) -> cplx {          // d_k
+        if (kg >= ke) return cplx{0.0, 0.0};
+        return ld_elem<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg);
+      });
   const int64_t* cmap = c.colmap + p.cm;
   const int64_t* cseg = c.colseg + p.cm;
   acc_foreach<CPLX, TN>(acc, [&](int m, int n, cplx v) {
