@@ -483,21 +483,29 @@ __device__ __forceinline__ double* shift_base(const Common& c, int sh) {
   return c.L + (CPLX ? 2 : 1) * c.stride * sh;
 }
 
-// Dense LDL^T of the panel's wp x wp diagonal block in LDS, then L_pp^{-1}.
-// 512 threads: step k scales column k once (l[k][r] = a[r][k] / d_k) and
-// then updates the trailing triangle a[r][j] -= a[r][k] l[j][k] with eight
-// threads per row.  The unit-lower inverse is then computed column by
-// column, one thread per column and no barriers: column t of L^{-1} is
-// x_t = 1, x_i = -sum_{t <= k < i} L[i][k] x_k, reading L from `l` and
-// writing x into the (no longer needed) strict lower part of `a`.
+// Dense LDL^T of the panel's wp x wp diagonal block in LDS, with L_pp^{-1}
+// accumulated along the way.  Step k (one barrier per step, 512 threads, row
+// r = t % 64 and every eighth column per thread):
+//   trailing update  A[r][j] -= d_k L[r][k] L[j][k]            k+1 < j < r
+//   next column      L[r][k+1] = (A[r][k+1] - d_k L[r][k] L[k+1][k]) / d_{k+1}
+//   pivots           D[j] -= d_k L[j][k]^2                     j > k (two buffers)
+//   inverse          X[r][t] -= L[r][k] X[k][t]  (t < k),  X[r][k] = -L[r][k]
+// X = L^{-1} is built from the elementary eliminations in the columns of A
+// that step k no longer needs; d_{k+1} is recomputed by every thread that
+// needs it from the previous step's values, so the next column's multipliers
+// are formed in the same step (look-ahead) and no second barrier is needed.
 constexpr int NTD = 512;
 
 template <bool CPLX>
 __global__ void __launch_bounds__(NTD) k_diag(Common c, PanelK p) {
-  __shared__ double a_re[64][LDP];   // a[col][row]: working matrix, then L^{-1}
+  __shared__ double a_re[64][LDP];   // a[col][row]: working matrix, then L^{-1} (strict lower)
   __shared__ double a_im[CPLX ? 64 : 1][LDP];
   __shared__ double l_re[64][LDP];   // l[col][row]: L (strict lower)
   __shared__ double l_im[CPLX ? 64 : 1][LDP];
+  __shared__ double dd_re[2][64];    // running diagonal, double-buffered by step parity
+  __shared__ double dd_im[2][CPLX ? 64 : 1];
+  __shared__ double pv_re[64];       // pivots d_k
+  __shared__ double pv_im[CPLX ? 64 : 1];
   const int sh = blockIdx.y;
   double* Ls = shift_base<CPLX>(c, sh);
   const int wp = p.wp;
@@ -509,6 +517,19 @@ __global__ void __launch_bounds__(NTD) k_diag(Common c, PanelK p) {
     if (r >= cc) v = ld_elem<CPLX>(Ls, dbase + (int64_t)cc * p.ld + r);
     a_re[cc][r] = v.re;
     if (CPLX) a_im[cc][r] = v.im;
+    if (r == cc) {
+      dd_re[0][r] = v.re;
+      if (CPLX) dd_im[0][r] = v.im;
+    }
+  }
+  __syncthreads();
+  auto inv = [](cplx d) -> cplx { return CPLX ? cinv(d) : cplx{1.0 / d.re, 0.0}; };
+  // column 0 of L
+  if (t > 0 && t < wp) {
+    const cplx d0{dd_re[0][0], CPLX ? dd_im[0][0] : 0.0};
+    const cplx v = cmul(cplx{a_re[0][t], CPLX ? a_im[0][t] : 0.0}, inv(d0));
+    l_re[0][t] = v.re;
+    if (CPLX) l_im[0][t] = v.im;
   }
   __syncthreads();
   const double wabs = sqrt(c.shifts[2 * sh] * c.shifts[2 * sh] + c.shifts[2 * sh + 1] * c.shifts[2 * sh + 1]);
@@ -517,25 +538,50 @@ __global__ void __launch_bounds__(NTD) k_diag(Common c, PanelK p) {
   int neg = 0;
   const int r = t & 63, cg = t >> 6;   // eight threads per row
   for (int k = 0; k < wp; ++k) {
-    const cplx d{a_re[k][k], CPLX ? a_im[k][k] : 0.0};
+    const int cur = k & 1, nxt = cur ^ 1;
+    const cplx dk{dd_re[cur][k], CPLX ? dd_im[cur][k] : 0.0};
     if (t == 0) {
-      const double ad = CPLX ? sqrt(d.re * d.re + d.im * d.im) : fabs(d.re);
+      const double ad = CPLX ? sqrt(dk.re * dk.re + dk.im * dk.im) : fabs(dk.re);
       if (!(ad >= thr) && bad == 0) bad = p.col0 + k + 1;
-      if (!CPLX && d.re < 0.0) ++neg;
+      if (!CPLX && dk.re < 0.0) ++neg;
+      pv_re[k] = dk.re;
+      if (CPLX) pv_im[k] = dk.im;
     }
-    if (t > k && t < wp) {
-      const cplx id = CPLX ? cinv(d) : cplx{1.0 / d.re, 0.0};
-      const cplx v = cmul(cplx{a_re[k][t], CPLX ? a_im[k][t] : 0.0}, id);
-      l_re[k][t] = v.re;
-      if (CPLX) l_im[k][t] = v.im;
-    }
-    __syncthreads();
     if (r > k && r < wp) {
-      const cplx lrk{a_re[k][r], CPLX ? a_im[k][r] : 0.0};
-      for (int j = k + 1 + cg; j <= r; j += NTD / 64) {
-        const cplx f = cmul(lrk, cplx{l_re[k][j], CPLX ? l_im[k][j] : 0.0});
+      const cplx lrk{l_re[k][r], CPLX ? l_im[k][r] : 0.0};
+      const cplx dl = cmul(dk, lrk);                 // d_k L[r][k]
+      // trailing columns j in (k+1, r): off-diagonal entries of A
+      for (int j = k + 2 + cg; j < r; j += NTD / 64) {
+        const cplx f = cmul(dl, cplx{l_re[k][j], CPLX ? l_im[k][j] : 0.0});
         a_re[j][r] -= f.re;
         if (CPLX) a_im[j][r] -= f.im;
+      }
+      if (cg == 0) {
+        // running diagonal of row r
+        const cplx f = cmul(dl, lrk);
+        dd_re[nxt][r] = dd_re[cur][r] - f.re;
+        if (CPLX) dd_im[nxt][r] = dd_im[cur][r] - f.im;
+      }
+      if (cg == 1 && r > k + 1) {
+        // look-ahead: L[r][k+1] with d_{k+1} formed from the previous values
+        const cplx lk1{l_re[k][k + 1], CPLX ? l_im[k][k + 1] : 0.0};
+        const cplx dk1n = cmul(cmul(dk, lk1), lk1);
+        const cplx dk1{dd_re[cur][k + 1] - dk1n.re, CPLX ? dd_im[cur][k + 1] - dk1n.im : 0.0};
+        const cplx f = cmul(dl, lk1);
+        const cplx arn{a_re[k + 1][r] - f.re, CPLX ? a_im[k + 1][r] - f.im : 0.0};
+        const cplx v = cmul(arn, inv(dk1));
+        l_re[k + 1][r] = v.re;
+        if (CPLX) l_im[k + 1][r] = v.im;
+      }
+      // inverse: columns t < k of X get the elimination of column k
+      for (int tc = cg; tc < k; tc += NTD / 64) {
+        const cplx f = cmul(lrk, cplx{a_re[tc][k], CPLX ? a_im[tc][k] : 0.0});
+        a_re[tc][r] -= f.re;
+        if (CPLX) a_im[tc][r] -= f.im;
+      }
+      if (cg == 2) {
+        a_re[k][r] = -lrk.re;
+        if (CPLX) a_im[k][r] = -lrk.im;
       }
     }
     __syncthreads();
@@ -545,22 +591,10 @@ __global__ void __launch_bounds__(NTD) k_diag(Common c, PanelK p) {
     if (bad) atomicCAS((unsigned long long*)&c.info[sh], 0ull, (unsigned long long)bad);
     if (!CPLX && neg) atomicAdd((unsigned long long*)&c.negc[sh], (unsigned long long)neg);
   }
-  if (t < wp) {
-    for (int i = t + 1; i < wp; ++i) {
-      cplx s{l_re[t][i], CPLX ? l_im[t][i] : 0.0};
-      for (int k = t + 1; k < i; ++k) {
-        const cplx q = cmul(cplx{l_re[k][i], CPLX ? l_im[k][i] : 0.0}, cplx{a_re[t][k], CPLX ? a_im[t][k] : 0.0});
-        s.re += q.re;
-        s.im += q.im;
-      }
-      a_re[t][i] = -s.re;
-      if (CPLX) a_im[t][i] = -s.im;
-    }
-  }
-  __syncthreads();
   for (int idx = t; idx < wp * wp; idx += NTD) {
     const int cc = idx / wp, rr = idx % wp;
-    if (rr >= cc) st_elem<CPLX>(Ls, dbase + (int64_t)cc * p.ld + rr, cplx{a_re[cc][rr], CPLX ? a_im[cc][rr] : 0.0});
+    if (rr > cc) st_elem<CPLX>(Ls, dbase + (int64_t)cc * p.ld + rr, cplx{a_re[cc][rr], CPLX ? a_im[cc][rr] : 0.0});
+    if (rr == cc) st_elem<CPLX>(Ls, dbase + (int64_t)cc * p.ld + rr, cplx{pv_re[cc], CPLX ? pv_im[cc] : 0.0});
   }
 }
 
