@@ -34,6 +34,9 @@ MULTI = {
     "serve": "Poisson request stream: sizes Zipf(1.2) over k*1000 basis functions, chain / honeycomb / "
              "cubic, 40 poles, 30% SCF-style repeats of a resident pattern, 16-shift inertia counts on "
              "new patterns, 250 GiB admission budget, 4 streams",
+    "dos": "honeycomb N=26624: DOS on 200 bins over [-1.05, 1.05] Ha from 201 inertia counts "
+           "(batched real LDL^T, 32 shifts per batch) and the LDOS matrix at 4 energies (eta = 1e-3 Ha, "
+           "one batched complex factorization + SelInv + pole sums)",
 }
 
 WORKLOADS = {
@@ -184,6 +187,44 @@ def run_batch(args):
     return res
 
 
+def run_dos(args):
+    import numpy as np
+    import torch
+    from paper_1405_0194_amd import binding as B
+    from paper_1405_0194_amd import dos as pdos
+    from paper_1405_0194_amd import lattice, tune
+    s = lattice.config_system(1)
+    a = tune.tuned_analysis(s, 60).bind()
+    H = torch.from_numpy(s.hval).cuda()
+    S = torch.from_numpy(s.sval).cuda()
+    edges = np.linspace(-1.05, 1.05, 201)
+    energies = np.array([-0.2, -0.05, 0.0, 0.1])
+    pdos.dos(a, H, S, edges[:33], batch=32)            # warm-up
+    torch.cuda.synchronize()
+    tds = []
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        centres, g, c = pdos.dos(a, H, S, edges, batch=32)
+        torch.cuda.synchronize()
+        tds.append(time.perf_counter() - t)
+    tls = []
+    for _ in range(max(1, args.steps)):
+        t = time.perf_counter()
+        out, tr, info = pdos.ldos(a, H, S, energies, 1e-3)
+        torch.cuda.synchronize()
+        tls.append(time.perf_counter() - t)
+    td, tl = float(np.median(tds)), float(np.median(tls))
+    return {"metric": "inertia counts/s (DOS) and LDOS energies/s", "value": round(len(edges) / td, 3),
+            "unit": "inertia-counts/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+            "ms_per_step": round(1e3 * td, 3), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64 (DOS), c128 (LDOS)", "data": "synthetic",
+            "config": {"workload": MULTI["dos"], "n": s.n, "bins": len(edges) - 1},
+            "dos_s": round(td, 4), "electrons_counted": int(c[-1] - c[0]),
+            "ldos": {"energies": len(energies), "seconds": round(tl, 4),
+                     "energies_per_s": round(len(energies) / tl, 3),
+                     "tr_GS": [round(float(x), 6) for x in tr[:, 0]]}}
+
+
 def run_serve(args):
     import torch
     from paper_1405_0194_amd import lattice
@@ -276,7 +317,10 @@ def main():
 
     if args.workload in MULTI:
         torch.cuda.set_device(0)
-        res = run_batch(args) if args.workload == "batch" else run_serve(args)
+        res = {"batch": run_batch, "serve": run_serve, "dos": run_dos}[args.workload](args)
+        if args.workload == "dos":      # its own metric and unit
+            print(json.dumps(res), flush=True)
+            return
         steps = args.steps if args.workload == "batch" else 1
         warm = args.warmup if args.workload == "batch" else 0
         line = {"metric": "pole-solves/sec (LDL^T+SelInv), FP64 MFMA %, p50/p99 request latency",

@@ -116,29 +116,35 @@ def bracket_from_counts(count_fn, Ne, lo, hi, beta, Q=16, dN=0.1, rounds=3, max_
     return res
 
 
+def inertia_counts(analysis, H, S, eps, L=None, work=None, stream=None, max_retry=4):
+    """#negative pivots of H - eps_q S for every q (batched real LDL^T on the
+    device).  A shift that hits a tiny pivot is moved by 1e-9 relative and
+    counted again (the count is piecewise constant in eps)."""
+    eps = np.array(eps, dtype=np.float64)
+    neg, info = B.inertia(analysis, H, S, eps, L=L, work=work, stream=stream)
+    for _ in range(max_retry):
+        bad = np.nonzero(info)[0]
+        if not len(bad):
+            break
+        scale = max(1.0, float(np.abs(eps).max()))
+        eps[bad] += 1e-9 * scale
+        neg2, info2 = B.inertia(analysis, H, S, eps[bad], L=L, work=work, stream=stream)
+        neg[bad] = neg2
+        info[bad] = info2
+    if np.any(info):
+        raise B.PxsError("inertia_counts", B.PXS_TINY_PIVOT, "tiny pivot persists after shifting")
+    return neg
+
+
 def inertia_bracket(analysis, H, S, Ne, lo, hi, beta, Q=16, dN=0.1, rounds=3, tol=None, L=None, work=None,
                     stream=None, max_retry=4):
     """Bracketing with N_inf from batched real LDL^T inertia counts on the
-    device.  A shift that hits a tiny pivot is moved by a small relative
-    amount and counted again (N_inf is piecewise constant)."""
+    device."""
     if L is None or work is None:
         L, work = analysis.buffers(Q, real=True, device=H.device)
 
     def count(eps):
-        eps = np.array(eps, dtype=np.float64)
-        neg, info = B.inertia(analysis, H, S, eps, L=L, work=work, stream=stream)
-        for _ in range(max_retry):
-            bad = np.nonzero(info)[0]
-            if not len(bad):
-                break
-            scale = max(1.0, float(np.abs(eps).max()))
-            eps[bad] += 1e-9 * scale
-            neg2, info2 = B.inertia(analysis, H, S, eps[bad], L=L, work=work, stream=stream)
-            neg[bad] = neg2
-            info[bad] = info2
-        if np.any(info):
-            raise B.PxsError("inertia_bracket", B.PXS_TINY_PIVOT, "tiny pivot persists after shifting")
-        return neg
+        return inertia_counts(analysis, H, S, eps, L=L, work=work, stream=stream, max_retry=max_retry)
 
     return bracket_from_counts(count, Ne, lo, hi, beta, Q=Q, dN=dN, rounds=rounds, tol=tol)
 
