@@ -273,6 +273,8 @@ def main():
     ap.add_argument("--leaf-cols", type=int, default=0)
     ap.add_argument("--selinv-streams", type=int, default=0)
     ap.add_argument("--selinv-chunk", type=int, default=0)
+    ap.add_argument("--hbm-budget-gib", type=float, default=260.0,
+                    help="device memory for factors + workspace; SelInv chunks its shifts beyond it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling the HBM byte counters)")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -351,6 +353,20 @@ def main():
     else:
         from paper_1405_0194_amd import tune
         a = tune.tuned_analysis(s, lattice.CONFIG_POLES[cfg])
+    # SelInv works on shift chunks when the whole batch's workspace would not
+    # fit beside the factors (the cubic bulk: 201 GB of factors for 80 shifts)
+    budget = int(args.hbm_budget_gib * 2**30)
+    need = a.info["bytes_per_shift"] * P + a.workspace_size(P)
+    if need > budget and not args.selinv_chunk:
+        for ch in (40, 20, 16, 10, 8, 5, 4, 2, 1):
+            if ch >= P:
+                continue
+            a2 = B.Analysis.from_system(s, **{**a.options, "selinv_chunk": ch})
+            if a2.info["bytes_per_shift"] * P + a2.workspace_size(P) <= budget:
+                a = a2
+                break
+        print(f"# SelInv chunk {a.options['selinv_chunk']} shifts to fit {args.hbm_budget_gib} GiB",
+              file=sys.stderr, flush=True)
     t_an = time.perf_counter() - t_an
     t_bind = time.perf_counter()
     a.bind()
