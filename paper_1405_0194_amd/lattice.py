@@ -66,16 +66,22 @@ class System:
         return int(self.rowind.shape[0])
 
     def dense(self):
-        """Dense symmetric H and S (float64), for small systems only."""
+        """Dense H and S (real symmetric, or complex Hermitian when the values
+        are complex: the upper triangle is the conjugate of the lower), for
+        small systems only."""
         n = self.n
-        H = np.zeros((n, n))
-        S = np.zeros((n, n))
+        H = np.zeros((n, n), dtype=self.hval.dtype)
+        S = np.zeros((n, n), dtype=self.sval.dtype)
         cols = np.repeat(np.arange(n), np.diff(self.colptr))
+        H[cols, self.rowind] = np.conj(self.hval)
+        S[cols, self.rowind] = np.conj(self.sval)
         H[self.rowind, cols] = self.hval
         S[self.rowind, cols] = self.sval
-        H[cols, self.rowind] = self.hval
-        S[cols, self.rowind] = self.sval
         return H, S
+
+    @property
+    def hermitian(self) -> bool:
+        return np.iscomplexobj(self.hval)
 
     def entry_cols(self) -> np.ndarray:
         return np.repeat(np.arange(self.n, dtype=np.int64), np.diff(self.colptr))
@@ -259,6 +265,39 @@ def make_system(kind: str, dims, orb: int, cutoff: float, seed: int,
                   hval=hv, sval=sv, blkptr=blkptr, coords=coords, orb=orb,
                   seed=seed, meta=dict(dims=dims, cutoff=cutoff, npairs=int(npair),
                                        periodic_axes=len(cellv)))
+
+
+def make_hermitian_system(kind: str, dims, orb: int, cutoff: float, seed: int,
+                          periodic: bool = True, dilute: float = 0.0, imag_scale: float = 0.5) -> System:
+    """A complex Hermitian pencil on the same lattice and pattern as
+    make_system: every stored (lower) entry gets an imaginary part
+    imag_scale * N(0,1) * |real part| (diagonal entries stay real), drawn from
+    a second stream seeded with seed + 1; then H is rescaled by its largest
+    absolute row sum and S is made diagonally dominant again, so the pencil's
+    spectrum stays inside [-1, 1] and S is Hermitian positive definite.
+    Stands in for k-point Hamiltonians (Bloch phases make H complex)."""
+    base = make_system(kind, dims, orb, cutoff, seed, periodic=periodic, dilute=dilute)
+    rng = np.random.default_rng(seed + 1)
+    rows = base.rowind.astype(np.int64)
+    cols = base.entry_cols()
+    offd = rows != cols
+    hv = base.hval.astype(np.complex128)
+    sv = base.sval.astype(np.complex128)
+    g = rng.standard_normal((2, rows.shape[0]))
+    hv[offd] += 1j * imag_scale * g[0][offd] * np.abs(base.hval[offd])
+    sv[offd] += 1j * imag_scale * g[1][offd] * np.abs(base.sval[offd])
+    n = base.n
+    absrow = np.zeros(n)
+    np.add.at(absrow, rows, np.abs(hv))
+    np.add.at(absrow, cols[offd], np.abs(hv[offd]))
+    hv = hv / absrow.max()
+    srow = np.zeros(n)
+    np.add.at(srow, rows[offd], np.abs(sv[offd]))
+    np.add.at(srow, cols[offd], np.abs(sv[offd]))
+    diag = ~offd
+    sv[diag] = 1.0 + srow[rows[diag]]
+    meta = dict(base.meta, hermitian=True, imag_scale=imag_scale)
+    return dataclasses.replace(base, hval=hv, sval=sv, meta=meta)
 
 
 def _abs_row_sum_max(colptr, rowind, v):
