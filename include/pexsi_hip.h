@@ -166,6 +166,23 @@ pxs_status pxs_factor(pxs_symbolic sym, const double* Hval, const double* Sval,
                       int32_t nshift, const pxs_c64* shifts, void* Lbuf, void* work,
                       int64_t* info, void* stream, pxs_numeric* out);
 
+/* Complex Hermitian H and S (k-point Hamiltonians; the structurally
+ * symmetric, non-symmetric variant named as future work in the paper's
+ * conclusion): A_l = H - shifts[l] S is factored as L D U without pivoting.
+ * Hval, Sval (device, nnz_lower complex): the lower triangle on the input
+ * pattern (the upper triangle is its conjugate; diagonal entries real).
+ * Lbuf and work sizes come from pxs_hermitian_sizes (Lbuf holds per shift
+ * the L region and a U^T region of the same layout).  The returned handle
+ * works with pxs_selinv (selected inverse of both triangles), pxs_pole_sum
+ * (complex output, see there), pxs_get_selected (lower triangle Z_l[i][j],
+ * i >= j), pxs_get_selected_upper (Z_l[j][i] at the same entries) and
+ * pxs_get_diag.  SelInv of a Hermitian handle runs on the given stream only.
+ * Errors and info as for pxs_factor. */
+pxs_status pxs_hermitian_sizes(pxs_symbolic sym, int32_t nshift, int64_t* lbuf_bytes, int64_t* work_bytes);
+pxs_status pxs_factor_hermitian(pxs_symbolic sym, const pxs_c64* Hval, const pxs_c64* Sval,
+                                int32_t nshift, const pxs_c64* shifts, void* Lbuf, void* work,
+                                int64_t* info, void* stream, pxs_numeric* out);
+
 /* Selected inversion in place (Sec. II.B step 4): afterwards Lbuf holds
  * Z_l = A_l^{-1} on the (supernodal) pattern of L for every shift. */
 pxs_status pxs_selinv(pxs_numeric num, void* stream);
@@ -174,12 +191,19 @@ pxs_status pxs_selinv(pxs_numeric num, void* stream);
  * out[g * nnz_lower + k] = Im sum_l weights[g * nshift + l] * Z_l[k]
  * (device output, input ordering).  traces (host, 2 * nsets, nullable):
  * traces[2g] = Tr(Gamma^g S), traces[2g+1] = Tr(Gamma^g H) over the full
- * symmetric matrices.  Requires pxs_selinv first. */
+ * symmetric matrices.  Requires pxs_selinv first.
+ * Hermitian handles: Gamma^g = (M - M^H) / 2i with M = sum_l w_{g,l} Z_l
+ * (the matrix imaginary part; entrywise Im for real pencils); out then holds
+ * nsets * nnz_lower complex values (2 doubles each, Gamma_ij for i >= j) and
+ * the traces are Re Tr(Gamma S), Re Tr(Gamma H). */
 pxs_status pxs_pole_sum(pxs_numeric num, int32_t nsets, const pxs_c64* weights,
                         double* out, double* traces, void* stream);
 
 /* Z_l on the input pattern (device out[nnz_lower], input ordering). */
 pxs_status pxs_get_selected(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream);
+/* Z_l[j][i] for every input entry (i, j), i >= j (equal to pxs_get_selected
+ * for real pencils). */
+pxs_status pxs_get_selected_upper(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream);
 
 /* D of shift l after pxs_factor (device out[n], new ordering). */
 pxs_status pxs_get_diag(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream);

@@ -71,6 +71,9 @@ def load():
         "pxs_selinv": (C.c_int, [_P, _P]),
         "pxs_pole_sum": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P]),
         "pxs_get_selected": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "pxs_get_selected_upper": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "pxs_hermitian_sizes": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "pxs_factor_hermitian": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
         "pxs_get_diag": (C.c_int, [_P, C.c_int32, _P, _P]),
         "pxs_inertia": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
         "pxs_density_matrix": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
@@ -300,6 +303,89 @@ class Factorization:
                 self._h = None
         except Exception:
             pass
+
+
+class HermitianFactorization:
+    """A batch of shifts of a complex Hermitian pencil factored as L D U
+    (and optionally inverted) in caller buffers.  H and S: complex128 device
+    tensors with the lower triangle on the input pattern."""
+
+    def __init__(self, analysis: Analysis, H, S, shifts, L=None, work=None, stream=None):
+        import torch
+        lib = load()
+        self._lib = lib
+        self.analysis = analysis
+        analysis.bind()
+        self.shifts = np.ascontiguousarray(shifts, dtype=np.complex128)
+        nshift = self.shifts.shape[0]
+        self.nshift = nshift
+        lb, wb = hermitian_sizes(analysis, nshift)
+        if L is None or work is None:
+            L = torch.empty(lb, dtype=torch.uint8, device=H.device)
+            work = torch.empty(wb, dtype=torch.uint8, device=H.device)
+        nnz = analysis.info["nnz_lower"]
+        for t, name in ((H, "H values"), (S, "S values")):
+            if t.dtype != torch.complex128 or t.numel() != nnz or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name}: need a contiguous complex128 device tensor of {nnz} entries")
+        _require(L, lb, "factor storage")
+        _require(work, wb, "workspace")
+        self.L, self.work = L, work
+        self.H, self.S = H, S
+        self.info = np.zeros(nshift, dtype=np.int64)
+        h = _P()
+        code = lib.pxs_factor_hermitian(analysis._h, _dptr(H), _dptr(S), nshift, _ptr(self.shifts), _dptr(L),
+                                        _dptr(work), _ptr(self.info), _stream(stream), C.byref(h))
+        _check("pxs_factor_hermitian", code, allow=(PXS_OK, PXS_TINY_PIVOT))
+        self._h = h
+
+    def diag(self, l, stream=None):
+        import torch
+        out = torch.empty(self.analysis.n, dtype=torch.complex128, device=self.L.device)
+        _check("pxs_get_diag", self._lib.pxs_get_diag(self._h, l, _dptr(out), _stream(stream)))
+        return out
+
+    def selinv(self, stream=None):
+        _check("pxs_selinv", self._lib.pxs_selinv(self._h, _stream(stream)))
+        return self
+
+    def selected(self, l, upper=False, stream=None):
+        """Z_l[i][j] (or Z_l[j][i] with upper) at the input entries i >= j."""
+        import torch
+        out = torch.empty(self.analysis.info["nnz_lower"], dtype=torch.complex128, device=self.L.device)
+        f = self._lib.pxs_get_selected_upper if upper else self._lib.pxs_get_selected
+        _check("pxs_get_selected", f(self._h, l, _dptr(out), _stream(stream)))
+        return out
+
+    def pole_sum(self, weights, stream=None):
+        """Gamma^g = (M - M^H) / 2i, M = sum_l omega_{g,l} Z_l: returns
+        ((nsets, nnz) complex tensor of Gamma_ij at the input entries,
+        traces (nsets, 2) = [Re Tr(G S), Re Tr(G H)])."""
+        import torch
+        weights = np.ascontiguousarray(weights, dtype=np.complex128)
+        nsets = weights.shape[0]
+        if weights.shape != (nsets, self.nshift):
+            raise ValueError("weights must be (nsets, nshift)")
+        nnz = self.analysis.info["nnz_lower"]
+        out = torch.empty(nsets * nnz, dtype=torch.complex128, device=self.L.device)
+        tr = np.zeros(2 * nsets)
+        _check("pxs_pole_sum", self._lib.pxs_pole_sum(self._h, nsets, _ptr(weights), _dptr(out), _ptr(tr),
+                                                       _stream(stream)))
+        return out.view(nsets, nnz), tr.reshape(nsets, 2)
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                self._lib.pxs_free_numeric(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+def hermitian_sizes(analysis: Analysis, nshift: int):
+    """(factor storage bytes, workspace bytes) of a Hermitian batch."""
+    lb, wb = C.c_int64(), C.c_int64()
+    _check("pxs_hermitian_sizes", load().pxs_hermitian_sizes(analysis._h, nshift, C.byref(lb), C.byref(wb)))
+    return lb.value, wb.value
 
 
 class Plan:

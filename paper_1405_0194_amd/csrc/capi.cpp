@@ -27,6 +27,7 @@ struct pxs_numeric_s {
   void* L = nullptr;
   void* work = nullptr;
   bool selinv_done = false;
+  bool herm = false;            // complex Hermitian factorization (L + U^T regions)
 };
 
 extern "C" void pxs_plan_free(struct pxs_plan_s* plan);
@@ -251,10 +252,54 @@ pxs_status pxs_factor(pxs_symbolic sym, const double* Hval, const double* Sval, 
   return PXS_OK;
 }
 
+pxs_status pxs_hermitian_sizes(pxs_symbolic sym, int32_t nshift, int64_t* lbuf_bytes, int64_t* work_bytes) {
+  if (!sym || nshift < 1 || nshift > pxs::MAX_SHIFTS) return PXS_EINVAL;
+  if (lbuf_bytes) *lbuf_bytes = pxs::herm_storage_bytes(sym->S, nshift);
+  if (work_bytes) *work_bytes = pxs::herm_work_bytes(sym->S, nshift);
+  return PXS_OK;
+}
+
+pxs_status pxs_factor_hermitian(pxs_symbolic sym, const pxs_c64* Hval, const pxs_c64* Sval, int32_t nshift,
+                                const pxs_c64* shifts, void* Lbuf, void* work, int64_t* info, void* stream,
+                                pxs_numeric* out) {
+  pxs_status s0 = check_numeric_args(sym, (const double*)Hval, (const double*)Sval, nshift, Lbuf, work);
+  if (s0 != PXS_OK) return s0;
+  if (!shifts || !out) return PXS_EINVAL;
+  for (int32_t l = 0; l < nshift; ++l)
+    if (!std::isfinite(shifts[l].re) || !std::isfinite(shifts[l].im)) return PXS_EINVAL;
+  pxs_numeric_s* h = new (std::nothrow) pxs_numeric_s;
+  if (!h) return PXS_ENOMEM;
+  h->S = &sym->S;
+  h->H = (const double*)Hval;
+  h->Sv = (const double*)Sval;
+  h->nshift = nshift;
+  h->herm = true;
+  h->shifts.assign((const double*)shifts, (const double*)shifts + 2 * nshift);
+  h->L = Lbuf;
+  h->work = work;
+  hipStream_t st = (hipStream_t)stream;
+  int e = pxs::run_factor_h(sym->S, h->H, h->Sv, nshift, h->shifts.data(), Lbuf, work, st);
+  if (e != 0) {
+    delete h;
+    return hip_fail(e);
+  }
+  *out = h;
+  if (info) {
+    hipError_t he = hipMemcpyAsync(info, (char*)work + pxs::WK_INFO, sizeof(int64_t) * nshift,
+                                   hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return hip_fail(he);
+    for (int32_t l = 0; l < nshift; ++l)
+      if (info[l] != 0) return PXS_TINY_PIVOT;
+  }
+  return PXS_OK;
+}
+
 pxs_status pxs_selinv(pxs_numeric num, void* stream) {
   if (!num) return PXS_EINVAL;
   if (num->selinv_done) return PXS_ESTATE;
-  int e = pxs::run_selinv(*num->S, num->nshift, num->L, num->work, (hipStream_t)stream);
+  int e = num->herm ? pxs::run_selinv_h(*num->S, num->nshift, num->L, num->work, (hipStream_t)stream)
+                    : pxs::run_selinv(*num->S, num->nshift, num->L, num->work, (hipStream_t)stream);
   if (e != 0) return hip_fail(e);
   num->selinv_done = true;
   return PXS_OK;
@@ -266,8 +311,10 @@ pxs_status pxs_pole_sum(pxs_numeric num, int32_t nsets, const pxs_c64* weights, 
   if (!num->selinv_done) return PXS_ESTATE;
   num->weights.assign((const double*)weights, (const double*)weights + 2 * nsets * num->nshift);
   hipStream_t st = (hipStream_t)stream;
-  int e = pxs::run_pole_sum(*num->S, num->nshift, num->L, num->work, num->H, num->Sv, nsets,
-                            num->weights.data(), out, st);
+  int e = num->herm ? pxs::run_pole_sum_h(*num->S, num->nshift, num->L, num->work, num->H, num->Sv, nsets,
+                                           num->weights.data(), out, st)
+                    : pxs::run_pole_sum(*num->S, num->nshift, num->L, num->work, num->H, num->Sv, nsets,
+                                        num->weights.data(), out, st);
   if (e != 0) return hip_fail(e);
   if (traces) {
     double t8[8];
@@ -282,7 +329,16 @@ pxs_status pxs_pole_sum(pxs_numeric num, int32_t nsets, const pxs_c64* weights, 
 
 pxs_status pxs_get_selected(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream) {
   if (!num || !out || shift < 0 || shift >= num->nshift) return PXS_EINVAL;
-  int e = pxs::run_gather(*num->S, shift, num->L, out, (hipStream_t)stream);
+  int e = num->herm ? pxs::run_gather_h(*num->S, shift, false, num->L, out, (hipStream_t)stream)
+                    : pxs::run_gather(*num->S, shift, num->L, out, (hipStream_t)stream);
+  if (e != 0) return hip_fail(e);
+  return PXS_OK;
+}
+
+pxs_status pxs_get_selected_upper(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream) {
+  if (!num || !out || shift < 0 || shift >= num->nshift) return PXS_EINVAL;
+  int e = num->herm ? pxs::run_gather_h(*num->S, shift, true, num->L, out, (hipStream_t)stream)
+                    : pxs::run_gather(*num->S, shift, num->L, out, (hipStream_t)stream);
   if (e != 0) return hip_fail(e);
   return PXS_OK;
 }
@@ -290,7 +346,8 @@ pxs_status pxs_get_selected(pxs_numeric num, int32_t shift, pxs_c64* out, void* 
 pxs_status pxs_get_diag(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream) {
   if (!num || !out || shift < 0 || shift >= num->nshift) return PXS_EINVAL;
   if (num->selinv_done) return PXS_ESTATE;
-  int e = pxs::run_get_diag(*num->S, shift, true, num->L, out, (hipStream_t)stream);
+  int e = num->herm ? pxs::run_get_diag_h(*num->S, shift, num->L, out, (hipStream_t)stream)
+                    : pxs::run_get_diag(*num->S, shift, true, num->L, out, (hipStream_t)stream);
   if (e != 0) return hip_fail(e);
   return PXS_OK;
 }

@@ -476,6 +476,7 @@ struct Common {
   double pivtol;
   double* G;               // dense Z_CC of the current supernode, per shift of a chunk
   int64_t gstride;         // doubles per shift in G
+  int64_t ut;              // Hermitian factorizations: elements from a shift's L region to its U^T region
 };
 
 template <bool CPLX>
@@ -966,7 +967,7 @@ __global__ void __launch_bounds__(NT) k_pole_sum(const double* __restrict__ L, i
         acc[g] += wr * z.y + wi * z.x;
       }
     }
-    const double mult = ediag[k] ? 1.0 : 2.0;
+    const double mult = ediag[k] == 1 ? 1.0 : 2.0;
     for (int g = 0; g < nsets; ++g) {
       // accumulate: add to the sums of earlier pole chunks (traces stay per chunk)
       out[(int64_t)g * nnz + k] = accumulate ? out[(int64_t)g * nnz + k] + acc[g] : acc[g];
@@ -1098,6 +1099,7 @@ Common make_common(const Symbolic& S, void* L, void* work) {
   c.pivtol = S.pivot_tol;
   c.G = nullptr;
   c.gstride = S.gather_per_shift / 8;
+  c.ut = 0;
   return c;
 }
 
@@ -1448,5 +1450,7 @@ int run_get_diag(const Symbolic& S, int shift, bool cplx, const void* L, void* o
   PXS_CHECK_LAUNCH();
   return 0;
 }
+
+#include "hermitian.inc"
 
 }  // namespace pxs

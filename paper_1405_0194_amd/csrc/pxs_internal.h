@@ -51,7 +51,7 @@ struct Symbolic {
   std::vector<int64_t> colseg;
   std::vector<int32_t> relpos;
   std::vector<int64_t> entry_off;    // input entry -> element offset
-  std::vector<int32_t> entry_diag;   // 1 on the diagonal, else 0
+  std::vector<int32_t> entry_diag;   // 1 on the diagonal; 2 if the storage holds the entry's transpose; else 0
 
   std::vector<Panel> panels;        // factor order; selected inversion runs backwards
   int64_t max_below = 0;            // max nb_rows over panels

@@ -502,7 +502,9 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
       const int32_t* it = std::lower_bound(first, lastp, hi);
       if (it == lastp || *it != hi) { msg = "internal: entry outside the pattern of L"; return -1; }
       S.entry_off[p] = S.off[J] + (int64_t)(lo - S.sfirst[J]) * S.ld[J] + (it - first);
-      S.entry_diag[p] = (rowind[p] == j) ? 1 : 0;
+      // 1: diagonal; 2: the entry's transpose is what is stored (its new
+      // row index precedes its new column index); 0: stored as given
+      S.entry_diag[p] = (rowind[p] == j) ? 1 : (a < b ? 2 : 0);
     }
   }
 

@@ -339,3 +339,45 @@ def test_graph_plan_replays_match_eager(torch_cuda):
         assert np.array_equal(out_g, out_e.cpu().numpy()), rep
         assert np.array_equal(tr_g, tr_e), rep
         assert np.all(info == 0)
+
+
+def test_maximum_batch_of_shifts(torch_cuda):
+    """4096 shifts (the largest batch) in one factorization + SelInv;
+    sampled shifts against the dense inverse."""
+    torch = torch_cuda
+    from paper_1405_0194_amd import binding as B
+    s = lattice.config_system(0)
+    Hd, Sd = s.dense()
+    rng = np.random.default_rng(4096)
+    shifts = rng.uniform(-1.2, 1.2, 4096) + 1j * rng.uniform(1e-3, 0.5, 4096)
+    say("case: chain N=256 with 4096 shifts")
+    a, f, H, S = _run(torch, s, shifts)
+    assert np.all(f.info == 0)
+    f.selinv()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for l in (0, 1, 1000, 2047, 4094, 4095):
+        z = f.selected(l).cpu().numpy()
+        zo = _entries(s, odense.shifted_inverse(Hd, Sd, shifts[l]))
+        worst = max(worst, _max_entry_err(z, zo))
+    say("max batch worst entry error", worst)
+    assert worst <= TOL
+
+
+def test_two_pole_density_matrix(torch_cuda):
+    """The smallest pole table (P = 2) through the fused call."""
+    torch = torch_cuda
+    from paper_1405_0194_amd import binding as B
+    s = lattice.config_system(0)
+    Hd, Sd = s.dense()
+    say("case: chain density matrix with P = 2")
+    a = B.Analysis.from_system(s)
+    H, S = _dev(torch, s.hval), _dev(torch, s.sval)
+    out, tr, info, sh, wt = B.density_matrix(a, H, S, BETA, 1.0, 0.0, 2, nsets=2)
+    assert np.all(info == 0)
+    ow, oom = opoles.pole_table(BETA, 1.0, 0.0, 2)
+    G = odense.gamma_route_a(Hd, Sd, ow, {k: oom[k] for k in ("rho", "E")})
+    cols = s.entry_cols()
+    out = out.cpu().numpy()
+    for g, name in enumerate(("rho", "E")):
+        assert _max_entry_err(out[g], G[name][s.rowind, cols]) <= TOL

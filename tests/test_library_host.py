@@ -194,3 +194,23 @@ def test_profile_rejects_bad_class_and_unopened_profile():
     assert (ms, n, w, b) == (0.0, 0, 0.0, 0.0)
     with pytest.raises(B.PxsError):
         B.profile_end()
+
+
+def test_empty_and_oversized_inputs_rejected():
+    lib = B.load()
+    # an empty matrix
+    with pytest.raises(B.PxsError) as ei:
+        B.Analysis(0, np.array([0]), np.array([], dtype=np.int32))
+    assert ei.value.code == B.PXS_EINVAL
+    a = B.Analysis(3, np.array([0, 2, 3, 4]), np.array([0, 1, 1, 2], dtype=np.int32))
+    # batch sizes outside 1..4096 shifts
+    import ctypes as C
+    b = C.c_int64()
+    for nshift in (0, -1, 4097):
+        assert lib.pxs_workspace_size(a._h, nshift, 0, C.byref(b)) == B.PXS_EINVAL
+    assert lib.pxs_workspace_size(a._h, 4096, 0, C.byref(b)) == B.PXS_OK
+    # the fused call checks the pole count before touching any buffer
+    for P, nsets in ((4098, 2), (3, 2), (0, 2), (40, 0), (40, 5)):
+        code = lib.pxs_density_matrix(a._h, None, None, 1000.0, 1.0, 0.0, P, nsets, None, None, None,
+                                      None, None, None, None, None)
+        assert code == B.PXS_EINVAL, (P, nsets)
