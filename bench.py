@@ -34,6 +34,9 @@ MULTI = {
     "serve": "Poisson request stream: sizes Zipf(1.2) over k*1000 basis functions, chain / honeycomb / "
              "cubic, 40 poles, 30% SCF-style repeats of a resident pattern, 16-shift inertia counts on "
              "new patterns, 250 GiB admission budget, 4 streams",
+    "hermitian": "complex Hermitian honeycomb pencil (same lattice and pattern as the honeycomb workload, "
+                 "imaginary parts 0.5 N(0,1) |Re| on off-diagonal entries), N=26624, 60 poles, one batch: "
+                 "L D U, two-sided selected inversion, Gamma = (M - M^H)/2i and Gamma^E with traces",
     "dos": "honeycomb N=26624: DOS on 200 bins over [-1.05, 1.05] Ha from 201 inertia counts "
            "(batched real LDL^T, 32 shifts per batch) and the LDOS matrix at 4 energies (eta = 1e-3 Ha, "
            "one batched complex factorization + SelInv + pole sums)",
@@ -225,6 +228,77 @@ def run_dos(args):
                      "tr_GS": [round(float(x), 6) for x in tr[:, 0]]}}
 
 
+def run_hermitian(args):
+    import numpy as np
+    import torch
+    from paper_1405_0194_amd import binding as B
+    from paper_1405_0194_amd import lattice, tune
+    P, beta, mu = 60, lattice.BETA_300K, 0.0
+    dE = 1.0 + abs(mu)
+    s = lattice.make_hermitian_system("honeycomb", (32, 32), 13, 3.0, lattice.CONFIG_SEED_BASE + 1)
+    a = tune.tuned_analysis(s, P).bind()
+    H = torch.from_numpy(s.hval).cuda()
+    S = torch.from_numpy(s.sval).cuda()
+    lb, wb = B.hermitian_sizes(a, P)
+    L = torch.empty(lb, dtype=torch.uint8, device="cuda")
+    W = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    sh, wt = B.poles(beta, dE, mu, P, 2)
+
+    def step():
+        f = B.HermitianFactorization(a, H, S, sh, L=L, work=W)
+        f.selinv()
+        return f.pole_sum(wt)
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        print(f"# warmup {i}: {time.perf_counter() - t:.3f}s", file=sys.stderr, flush=True)
+    B.profile_begin(args.profile_kernel)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        out, tr = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+        print(f"# step {i}: {lat[-1]:.3f}s  Tr(GS)={tr[0, 0]:.6f}", file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t0
+    kms, kl, kw, kb = B.profile_end(with_bytes=True)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    f = B.HermitianFactorization(a, H, S, sh, L=L, work=W)
+    e[1].record()
+    f.selinv()
+    e[2].record()
+    f.pole_sum(wt)
+    e[3].record()
+    torch.cuda.synchronize()
+    # L D U does the full Schur complement and SelInv both triangles: twice
+    # the complex-symmetric operation count
+    flops_shift = 2.0 * (a.info["flops_factor"] + a.info["flops_selinv"])
+    solves = P * args.steps
+    tfl = flops_shift * solves / elapsed / 1e12
+    avg = kms / max(kl, 1)
+    ach = (kw / max(kl, 1)) / (avg / 1e3) / 1e12 if kl else 0.0
+    return dict(value=round(solves / elapsed, 4), ms_per_step=round(1e3 * elapsed / args.steps, 3),
+                path_tflops=round(tfl, 3), fp64_mfma_pct=round(100.0 * tfl / PEAK_FP64_TFLOPS, 2),
+                latency_s={"p50": round(float(np.percentile(lat, 50)), 4),
+                           "p99": round(float(np.percentile(lat, 99)), 4)},
+                phases_ms={"assemble_factor_ms": round(e[0].elapsed_time(e[1]), 2),
+                           "selinv_ms": round(e[1].elapsed_time(e[2]), 2),
+                           "pole_sum_ms": round(e[2].elapsed_time(e[3]), 2)},
+                electrons=round(float(tr[0, 0]), 6),
+                roofline={"kernel": args.profile_kernel, "bound": "mfma", "achieved": round(ach, 3),
+                          "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / PEAK_FP64_TFLOPS, 4),
+                          "avg_launch_ms": round(avg, 4), "launches": kl, "traffic": None,
+                          "algorithmic_bytes_per_launch": round(kb / max(kl, 1))},
+                config={"workload": MULTI["hermitian"], "n": s.n, "poles": P,
+                        "factor_storage_GB": round(lb / 1e9, 1),
+                        "tflop_per_shift": round(flops_shift / 1e12, 4)})
+
+
 def run_serve(args):
     import torch
     from paper_1405_0194_amd import lattice
@@ -319,12 +393,13 @@ def main():
 
     if args.workload in MULTI:
         torch.cuda.set_device(0)
-        res = {"batch": run_batch, "serve": run_serve, "dos": run_dos}[args.workload](args)
+        res = {"batch": run_batch, "serve": run_serve, "dos": run_dos,
+               "hermitian": run_hermitian}[args.workload](args)
         if args.workload == "dos":      # its own metric and unit
             print(json.dumps(res), flush=True)
             return
-        steps = args.steps if args.workload == "batch" else 1
-        warm = args.warmup if args.workload == "batch" else 0
+        steps = args.steps if args.workload in ("batch", "hermitian") else 1
+        warm = args.warmup if args.workload in ("batch", "hermitian") else 0
         line = {"metric": "pole-solves/sec (LDL^T+SelInv), FP64 MFMA %, p50/p99 request latency",
                 "value": res.pop("value"), "unit": "pole-solves/s", "n_gpus": 1, "steps": steps,
                 "warmup": warm, "ms_per_step": res.pop("ms_per_step"), "higher_is_better": True,
