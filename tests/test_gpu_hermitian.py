@@ -39,11 +39,15 @@ def _err(x, y):
 CASES = {
     "chain": lambda: lattice.make_hermitian_system("chain", 64, 4, 2.0, 11),
     "honeycomb": lambda: lattice.make_hermitian_system("honeycomb", (6, 5), 13, 3.0, 12),
+    # 13 supernodes: independent subtrees of SelInv on up to 8 streams
+    "honeycomb87": lambda: lattice.make_hermitian_system("honeycomb", (8, 7), 13, 3.0, 13),
 }
 
 
 @pytest.mark.parametrize("name,akw", [("chain", {}), ("honeycomb", {}),
-                                      ("honeycomb", dict(leaf_cols=256, panel_width=32))])
+                                      ("honeycomb", dict(leaf_cols=256, panel_width=32)),
+                                      ("honeycomb87", dict(leaf_cols=32, selinv_streams=8)),
+                                      ("honeycomb87", dict(leaf_cols=32, selinv_streams=1))])
 def test_hermitian_selected_inverse_both_triangles(torch_cuda, name, akw):
     torch = torch_cuda
     from paper_1405_0194_amd import binding as B
@@ -121,3 +125,90 @@ def test_real_pencil_through_hermitian_path_matches_symmetric_path(torch_cuda):
         zs = fs.selected(l).cpu().numpy()
         assert _err(fh.selected(l).cpu().numpy(), zs) <= TOL
         assert _err(fh.selected(l, upper=True).cpu().numpy(), zs) <= TOL
+
+
+def _dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def test_hermitian_single_column_and_diagonal_pencil(torch_cuda):
+    torch = torch_cuda
+    from paper_1405_0194_amd import binding as B
+    say("case: hermitian single column")
+    a = B.Analysis(1, np.array([0, 1]), np.array([0]))
+    w = 0.1 + 0.2j
+    f = B.HermitianFactorization(a, _dev(torch, np.array([0.3 + 0j])), _dev(torch, np.array([2.0 + 0j])),
+                                 np.array([w]))
+    f.selinv()
+    for upper in (False, True):
+        z = f.selected(0, upper=upper).cpu().numpy()
+        assert abs(z[0] - 1.0 / (0.3 - w * 2.0)) < 1e-15
+    say("case: hermitian diagonal pencil")
+    n = 130
+    rng = np.random.default_rng(9)
+    h = rng.uniform(-0.9, 0.9, n) + 0j
+    sd = rng.uniform(1.0, 2.0, n) + 0j
+    a = B.Analysis(n, np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32))
+    shifts = np.array([0.1 + 0.01j, 0.1 - 0.01j, -0.5 + 0.2j])
+    f = B.HermitianFactorization(a, _dev(torch, h), _dev(torch, sd), shifts)
+    f.selinv()
+    for l, w in enumerate(shifts):
+        for upper in (False, True):
+            z = f.selected(l, upper=upper).cpu().numpy()
+            assert np.allclose(z, 1.0 / (h - w * sd), rtol=1e-14, atol=0)
+
+
+def _herm_identity_residual(system, w, zl, zu):
+    """max_i |sum_k A_ik Z_ki - 1| over the input pattern of a Hermitian
+    pencil: the stored lower entry (r, c) gives A_rc = H_rc - w S_rc (times
+    Z_cr, the upper extraction) to row r and A_cr = conj(H_rc) - w conj(S_rc)
+    (times Z_rc, the lower extraction) to row c."""
+    n = system.n
+    cols = system.entry_cols()
+    rows = system.rowind.astype(np.int64)
+    a_lo = system.hval - w * system.sval
+    a_up = np.conj(system.hval) - w * np.conj(system.sval)
+    acc = np.zeros(n, dtype=np.complex128)
+    mag = np.zeros(n)
+    np.add.at(acc, rows, a_lo * zu)
+    np.add.at(mag, rows, np.abs(a_lo * zu))
+    off = rows != cols
+    np.add.at(acc, cols[off], a_up[off] * zl[off])
+    np.add.at(mag, cols[off], np.abs(a_up[off] * zl[off]))
+    return float(np.max(np.abs(acc - 1.0) / np.maximum(mag, 1.0)))
+
+
+def test_hermitian_full_size_bench_configuration(torch_cuda):
+    """The Hermitian benchmark workload itself (honeycomb N=26,624, 60 poles
+    in one batch, SelInv on the default streams): properties that hold at any
+    size."""
+    torch = torch_cuda
+    from paper_1405_0194_amd import binding as B
+    s = lattice.make_hermitian_system("honeycomb", (32, 32), 13, 3.0, lattice.CONFIG_SEED_BASE + 1)
+    mu = 0.0
+    dE = 1.0 + abs(mu)
+    P = 60
+    a = B.Analysis.from_system(s)
+    sh, wt = B.poles(BETA, dE, mu, P, 2)
+    say("case: full-size hermitian honeycomb N=26624 P=60")
+    f = B.HermitianFactorization(a, _dev(torch, s.hval), _dev(torch, s.sval), sh)
+    assert np.all(f.info == 0)
+    f.selinv()
+    order = np.argsort(sh.imag)
+    for l in list(order[:2]) + [int(order[P // 2]), int(order[-1])]:
+        zl = f.selected(int(l)).cpu().numpy()
+        zu = f.selected(int(l), upper=True).cpu().numpy()
+        r = _herm_identity_residual(s, sh[l], zl, zu)
+        say("shift", l, "Im w", sh[l].imag, "diag(AZ)-1 residual", r)
+        assert r <= 1e-11
+    out, tr = f.pole_sum(wt)
+    e_rho = opoles.expansion_error(BETA, dE, mu, P)
+    e_E = opoles.expansion_error(BETA, dE, mu, P, g="E")
+    bound = s.n * (1.0 * e_rho + e_E) + 1e-8 * abs(tr[0, 1])
+    say("traces", tr, "bound", bound)
+    assert abs(tr[0, 1] - tr[1, 0]) <= bound
+    assert 0.0 < tr[0, 0] < 2.0 * s.n
+    # Gamma is Hermitian: its diagonal is real
+    cols = s.entry_cols()
+    dg = out[0].cpu().numpy()[s.rowind == cols]
+    assert np.max(np.abs(dg.imag)) <= 1e-12 * np.max(np.abs(dg.real))
