@@ -162,18 +162,47 @@ class Solver:
             e["buffers"][kind] = b
         return b[1], b[2]
 
+    def check_overlap(self, H, S, blocks=None, coords=None, stream=None):
+        """Whether S is positive definite, as the pencil needs (Sec. II.A),
+        checked on the device on the pattern of (H, S): real S by the
+        inertia of S (Sylvester: the number of negative pivots of its
+        L D L^T), complex Hermitian S by the pivots of its L D U, which are
+        real and all positive exactly when S is.  Returns (ok, number of
+        non-positive pivots, tiny-pivot column or 0)."""
+        import torch
+        n, colptr, rowind, hval, sval = lower_csc(H, S)
+        e = self._entry(n, colptr, rowind, blocks, coords)
+        a = e["analysis"]
+        Sd = torch.from_numpy(sval).to(self.device)
+        Z = torch.zeros_like(Sd)
+        if np.iscomplexobj(sval):
+            f = B.HermitianFactorization(a, Sd, Z, np.array([0j]), stream=stream)
+            info = int(f.info[0])
+            d = f.diag(0, stream=stream).cpu().numpy()
+            bad = int(np.sum(d.real <= 0.0))
+        else:
+            neg, inf = B.inertia(a, Sd, Z, np.array([0.0]), stream=stream)
+            info, bad = int(inf[0]), int(neg[0])
+        return info == 0 and bad == 0, bad, info
+
     def density_matrix(self, H, S, mu, beta, P, outputs=("rho", "E"), dE=None, blocks=None, coords=None,
-                       stream=None):
+                       stream=None, check_overlap=False):
         """Returns (*matrices in the order of `outputs`, traces dict).  Each
         matrix is a torch sparse CSC tensor of the lower triangle of the
         union pattern on the device (float64, complex128 for Hermitian
         input).  traces: N = Tr(G S), Eband = Tr(G H), and with the sets
         asked for TrES = Tr(G^E S), free_energy = Tr(G^F S) + mu N,
-        dN_dmu = Tr(G^d S); info = per-shift tiny-pivot columns (0 = none)."""
+        dN_dmu = Tr(G^d S); info = per-shift tiny-pivot columns (0 = none).
+        check_overlap runs check_overlap first and raises ValueError when S
+        is not positive definite."""
         import torch
         outputs = tuple(outputs)
         if not outputs or any(o not in SETS for o in outputs):
             raise ValueError(f"outputs must be a non-empty subset of {SETS}")
+        if check_overlap:
+            ok, bad, info = self.check_overlap(H, S, blocks=blocks, coords=coords, stream=stream)
+            if not ok:
+                raise ValueError(f"S is not positive definite: {bad} non-positive pivots, tiny pivot at {info}")
         nsets = 1 + max(SETS.index(o) for o in outputs)
         n, colptr, rowind, hval, sval = lower_csc(H, S)
         herm = np.iscomplexobj(hval)
@@ -216,10 +245,11 @@ class Solver:
 _default = None
 
 
-def density_matrix(H, S, mu, beta, P, outputs=("rho", "E"), dE=None, blocks=None, coords=None, stream=None):
+def density_matrix(H, S, mu, beta, P, outputs=("rho", "E"), dE=None, blocks=None, coords=None, stream=None,
+                   check_overlap=False):
     """Solver.density_matrix on a module-level solver (device cuda)."""
     global _default
     if _default is None:
         _default = Solver()
     return _default.density_matrix(H, S, mu, beta, P, outputs=outputs, dE=dE, blocks=blocks, coords=coords,
-                                   stream=stream)
+                                   stream=stream, check_overlap=check_overlap)

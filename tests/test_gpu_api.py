@@ -100,3 +100,44 @@ def test_api_hermitian_pencil(torch_cuda):
     tS, tH = oherm.traces(G["rho"], Hd, Sd)
     assert abs(tr["N"] - tS) <= 1e-10 * abs(tS)
     assert abs(tr["Eband"] - tH) <= 1e-10 * max(1.0, abs(tH))
+
+
+@pytest.mark.parametrize("hermitian", [False, True])
+def test_overlap_check_counts_negative_eigenvalues(torch_cuda, hermitian):
+    """S shifted down by c I has #{lambda_i(S) < c} negative pivots
+    (Sylvester); the unshifted S passes."""
+    import scipy.linalg as sla
+    from paper_1405_0194_amd import api
+    mk = lattice.make_hermitian_system if hermitian else lattice.make_system
+    s = mk("honeycomb", (3, 2), 5, 3.0, 43)
+    Hd, Sd = s.dense()
+    lam = sla.eigvalsh(Sd)
+    solver = api.Solver()
+    say(f"case: overlap check hermitian={hermitian} N={s.n}")
+    ok, bad, info = solver.check_overlap(sps.csr_matrix(Hd), sps.csr_matrix(Sd))
+    assert ok and bad == 0 and info == 0
+    c = 0.5 * (lam[3] + lam[4])          # four eigenvalues below c
+    Sbad = Sd - c * np.eye(s.n)
+    ok, bad, info = solver.check_overlap(sps.csr_matrix(Hd), sps.csr_matrix(Sbad))
+    assert not ok and info == 0 and bad == 4
+    with pytest.raises(ValueError):
+        solver.density_matrix(sps.csr_matrix(Hd), sps.csr_matrix(Sbad), 0.0, BETA, 10, dE=2.0,
+                              check_overlap=True)
+
+
+def test_api_runs_are_bitwise_reproducible(torch_cuda):
+    """Two calls on the same input give identical bits (owner-computes
+    updates, fixed reduction orders, SelInv on several streams)."""
+    import torch
+    from paper_1405_0194_amd import api
+    s = lattice.make_system("honeycomb", (6, 5), 13, 3.0, 44)
+    Hd, Sd = s.dense()
+    Ht = torch.from_numpy(Hd).to_sparse_csr().cuda()
+    St = torch.from_numpy(Sd).to_sparse_csr().cuda()
+    solver = api.Solver(leaf_cols=64, selinv_streams=4)
+    say(f"case: run-twice determinism N={s.n}")
+    r1, e1, t1 = solver.density_matrix(Ht, St, 0.0, BETA, 40)
+    v1, w1 = r1.values().clone(), e1.values().clone()
+    r2, e2, t2 = solver.density_matrix(Ht, St, 0.0, BETA, 40)
+    assert torch.equal(v1, r2.values()) and torch.equal(w1, e2.values())
+    assert t1["N"] == t2["N"] and t1["Eband"] == t2["Eband"]
