@@ -19,6 +19,7 @@ Tr(G S), Tr(G H) (eq. Nmu and the band energy), Tr(G^E S), the free energy
 Tr(G^F S) + mu N and N'(mu) = Tr(G^d S) (Sec. II.C) for the sets asked for.
 Every numerical step runs in the HIP library.
 """
+import contextlib
 import hashlib
 
 import numpy as np
@@ -119,6 +120,15 @@ def spectrum_bound(colptr, rowind, hval, sval):
     return float(np.max(hrow)) / lo
 
 
+def _on(stream):
+    """Makes stream torch's current stream for the block (None: unchanged),
+    so uploads, allocations and the library's launches share one stream."""
+    if stream is None:
+        return contextlib.nullcontext()
+    import torch
+    return torch.cuda.stream(stream)
+
+
 class Solver:
     """Keeps one symbolic analysis per sparsity pattern (bound to the
     device) and the last factor/workspace buffers of each; analysis options
@@ -169,20 +179,21 @@ class Solver:
         L D L^T), complex Hermitian S by the pivots of its L D U, which are
         real and all positive exactly when S is.  Returns (ok, number of
         non-positive pivots, tiny-pivot column or 0)."""
-        import torch
         n, colptr, rowind, hval, sval = lower_csc(H, S)
-        e = self._entry(n, colptr, rowind, blocks, coords)
-        a = e["analysis"]
-        Sd = torch.from_numpy(sval).to(self.device)
-        Z = torch.zeros_like(Sd)
-        if np.iscomplexobj(sval):
-            f = B.HermitianFactorization(a, Sd, Z, np.array([0j]), stream=stream)
-            info = int(f.info[0])
-            d = f.diag(0, stream=stream).cpu().numpy()
-            bad = int(np.sum(d.real <= 0.0))
-        else:
-            neg, inf = B.inertia(a, Sd, Z, np.array([0.0]), stream=stream)
-            info, bad = int(inf[0]), int(neg[0])
+        with _on(stream):
+            import torch
+            e = self._entry(n, colptr, rowind, blocks, coords)
+            a = e["analysis"]
+            Sd = torch.from_numpy(sval).to(self.device)
+            Z = torch.zeros_like(Sd)
+            if np.iscomplexobj(sval):
+                f = B.HermitianFactorization(a, Sd, Z, np.array([0j]))
+                info = int(f.info[0])
+                d = f.diag(0).cpu().numpy()
+                bad = int(np.sum(d.real <= 0.0))
+            else:
+                neg, inf = B.inertia(a, Sd, Z, np.array([0.0]))
+                info, bad = int(inf[0]), int(neg[0])
         return info == 0 and bad == 0, bad, info
 
     def density_matrix(self, H, S, mu, beta, P, outputs=("rho", "E"), dE=None, blocks=None, coords=None,
@@ -194,13 +205,19 @@ class Solver:
         asked for TrES = Tr(G^E S), free_energy = Tr(G^F S) + mu N,
         dN_dmu = Tr(G^d S); info = per-shift tiny-pivot columns (0 = none).
         check_overlap runs check_overlap first and raises ValueError when S
-        is not positive definite."""
+        is not positive definite.  stream: a torch.cuda.Stream for every
+        upload, allocation and launch of the call (default: the current
+        stream)."""
+        with _on(stream):
+            return self._density_matrix(H, S, mu, beta, P, outputs, dE, blocks, coords, check_overlap)
+
+    def _density_matrix(self, H, S, mu, beta, P, outputs, dE, blocks, coords, check_overlap):
         import torch
         outputs = tuple(outputs)
         if not outputs or any(o not in SETS for o in outputs):
             raise ValueError(f"outputs must be a non-empty subset of {SETS}")
         if check_overlap:
-            ok, bad, info = self.check_overlap(H, S, blocks=blocks, coords=coords, stream=stream)
+            ok, bad, info = self.check_overlap(H, S, blocks=blocks, coords=coords)
             if not ok:
                 raise ValueError(f"S is not positive definite: {bad} non-positive pivots, tiny pivot at {info}")
         nsets = 1 + max(SETS.index(o) for o in outputs)
@@ -218,15 +235,14 @@ class Solver:
         if herm:
             L, W = self._buffers(e, "herm", P)
             sh, wt = B.poles(beta, dE, mu, P, nsets)
-            f = B.HermitianFactorization(a, Hd, Sd, sh, L=L, work=W, stream=stream)
+            f = B.HermitianFactorization(a, Hd, Sd, sh, L=L, work=W)
             info = f.info.copy()
-            f.selinv(stream=stream)
-            out, tr = f.pole_sum(wt, stream=stream)
+            f.selinv()
+            out, tr = f.pole_sum(wt)
             del f
         else:
             L, W = self._buffers(e, "real", P)
-            out, tr, info, sh, wt = B.density_matrix(a, Hd, Sd, beta, dE, mu, P, nsets=nsets, L=L, work=W,
-                                                     stream=stream)
+            out, tr, info, sh, wt = B.density_matrix(a, Hd, Sd, beta, dE, mu, P, nsets=nsets, L=L, work=W)
         mats = []
         for o in outputs:
             g = SETS.index(o)

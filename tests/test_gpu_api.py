@@ -141,3 +141,9 @@ def test_api_runs_are_bitwise_reproducible(torch_cuda):
     r2, e2, t2 = solver.density_matrix(Ht, St, 0.0, BETA, 40)
     assert torch.equal(v1, r2.values()) and torch.equal(w1, e2.values())
     assert t1["N"] == t2["N"] and t1["Eband"] == t2["Eband"]
+    # a caller's side stream: uploads, buffers and launches all on it
+    side = torch.cuda.Stream()
+    r3, e3, t3 = solver.density_matrix(Ht, St, 0.0, BETA, 40, stream=side)
+    side.synchronize()
+    assert torch.equal(v1, r3.values()) and torch.equal(w1, e3.values())
+    assert t1["N"] == t3["N"]
