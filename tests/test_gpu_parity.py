@@ -280,20 +280,22 @@ def _diag_identity_residual(system, w, z):
     return float(np.max(np.abs(acc - 1.0) / np.maximum(mag, 1.0)))
 
 
-def test_full_size_honeycomb_bench_configuration(torch_cuda):
-    """The benchmark workload itself (honeycomb N=26,624, 60 poles in one
-    batch): properties that hold at any size."""
-    torch = torch_cuda
+def _full_size_check(torch, cfg, **akw):
+    """One density matrix of a full-size workload (mu = 0, 2 weight sets):
+    sum_k A_ik Z_ki = 1 on the input pattern for the shifts nearest to and
+    farthest from the real axis, Tr(G H) against Tr(G^E S) within the
+    expansion errors, and 0 < Tr(G S) < 2N."""
     from paper_1405_0194_amd import binding as B
-    s = lattice.config_system(1)
+    torch.cuda.empty_cache()
+    s = lattice.config_system(cfg)
     mu = 0.0
     dE = 1.0 + abs(mu)
-    P = lattice.CONFIG_POLES[1]
-    a = B.Analysis.from_system(s)
+    P = lattice.CONFIG_POLES[cfg]
+    a = B.Analysis.from_system(s, **akw)
     H = _dev(torch, s.hval)
     S = _dev(torch, s.sval)
     sh, wt = B.poles(BETA, dE, mu, P, 2)
-    say("case: full-size honeycomb N=26624 P=60")
+    say(f"case: full-size config {cfg} N={s.n} P={P} {akw}")
     f = B.Factorization(a, H, S, sh)
     assert np.all(f.info == 0)
     f.selinv()
@@ -310,6 +312,20 @@ def test_full_size_honeycomb_bench_configuration(torch_cuda):
     say("traces", tr, "bound", bound)
     assert abs(tr[0, 1] - tr[1, 0]) <= bound
     assert 0.0 < tr[0, 0] < 2.0 * s.n
+    del f, H, S
+    torch.cuda.empty_cache()
+
+
+def test_full_size_honeycomb_bench_configuration(torch_cuda):
+    """The benchmark workload itself (honeycomb N=26,624, 60 poles in one
+    batch, the launch configuration the benchmark times)."""
+    _full_size_check(torch_cuda, 1)
+
+
+def test_full_size_cubic_configuration(torch_cuda):
+    """The cubic bulk (N=22,464, 80 poles, mu inside the dense spectrum) at
+    full size: 187 GiB of factors, SelInv in chunks of 16 shifts."""
+    _full_size_check(torch_cuda, 2, selinv_chunk=16)
 
 
 def test_graph_plan_replays_match_eager(torch_cuda):
