@@ -216,6 +216,18 @@ pxs_status pxs_inertia(pxs_symbolic sym, const double* Hval, const double* Sval,
                        int32_t nshift, const double* eps, void* Lbuf, void* work,
                        int64_t* neg_count, int64_t* info, void* stream);
 
+/* Inertia counts of a complex Hermitian pencil (Sec. II.C for Hermitian H,
+ * S): the L D U factorization of H - eps[q] S (a Hermitian matrix at a real
+ * shift, so D is real up to rounding) and neg_count[q] = #{k : Re d_k < 0}
+ * (host), which by Sylvester's law is the number of eigenvalues of the
+ * pencil below eps[q].  Hval, Sval: device complex values on the input
+ * pattern as for pxs_factor_hermitian; Lbuf and work sized by
+ * pxs_hermitian_sizes(nshift).  info and errors as for pxs_inertia.
+ * Synchronises. */
+pxs_status pxs_inertia_hermitian(pxs_symbolic sym, const pxs_c64* Hval, const pxs_c64* Sval,
+                                 int32_t nshift, const double* eps, void* Lbuf, void* work,
+                                 int64_t* neg_count, int64_t* info, void* stream);
+
 /* Fused: poles + factor + selinv + pole sums, with the buffers above;
  * shifts/weights (host, nullable) receive the pole table used. */
 pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double* Sval,

@@ -76,6 +76,7 @@ def load():
         "pxs_factor_hermitian": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
         "pxs_get_diag": (C.c_int, [_P, C.c_int32, _P, _P]),
         "pxs_inertia": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+        "pxs_inertia_hermitian": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
         "pxs_density_matrix": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
                                          C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
         "pxs_plan_create": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P]),
@@ -461,6 +462,33 @@ def inertia(analysis: Analysis, H, S, eps, L=None, work=None, stream=None):
     code = lib.pxs_inertia(analysis._h, _dptr(H), _dptr(S), q, _ptr(eps), _dptr(L), _dptr(work),
                            _ptr(neg), _ptr(info), _stream(stream))
     _check("pxs_inertia", code, allow=(PXS_OK, PXS_TINY_PIVOT))
+    return neg, info
+
+
+def inertia_hermitian(analysis: Analysis, H, S, eps, L=None, work=None, stream=None):
+    """Counts #{k : Re d_k < 0} of the L D U of the Hermitian H - eps_q S for
+    each q (host int64 array) and the per-shift tiny-pivot info.  H, S:
+    complex128 device tensors on the input pattern."""
+    import torch
+    lib = load()
+    analysis.bind()
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    q = eps.shape[0]
+    lb, wb = hermitian_sizes(analysis, q)
+    if L is None or work is None:
+        L = torch.empty(lb, dtype=torch.uint8, device=H.device)
+        work = torch.empty(wb, dtype=torch.uint8, device=H.device)
+    nnz = analysis.info["nnz_lower"]
+    for t, name in ((H, "H values"), (S, "S values")):
+        if t.dtype != torch.complex128 or t.numel() != nnz or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: need a contiguous complex128 device tensor of {nnz} entries")
+    _require(L, lb, "factor storage")
+    _require(work, wb, "workspace")
+    neg = np.zeros(q, dtype=np.int64)
+    info = np.zeros(q, dtype=np.int64)
+    code = lib.pxs_inertia_hermitian(analysis._h, _dptr(H), _dptr(S), q, _ptr(eps), _dptr(L), _dptr(work),
+                                     _ptr(neg), _ptr(info), _stream(stream))
+    _check("pxs_inertia_hermitian", code, allow=(PXS_OK, PXS_TINY_PIVOT))
     return neg, info
 
 

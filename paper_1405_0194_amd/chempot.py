@@ -118,17 +118,19 @@ def bracket_from_counts(count_fn, Ne, lo, hi, beta, Q=16, dN=0.1, rounds=3, max_
 
 def inertia_counts(analysis, H, S, eps, L=None, work=None, stream=None, max_retry=4):
     """#negative pivots of H - eps_q S for every q (batched real LDL^T on the
-    device).  A shift that hits a tiny pivot is moved by 1e-9 relative and
-    counted again (the count is piecewise constant in eps)."""
+    device; for complex Hermitian H, S the batched L D U, whose pivots are
+    real at real shifts).  A shift that hits a tiny pivot is moved by 1e-9
+    relative and counted again (the count is piecewise constant in eps)."""
     eps = np.array(eps, dtype=np.float64)
-    neg, info = B.inertia(analysis, H, S, eps, L=L, work=work, stream=stream)
+    count = B.inertia_hermitian if H.is_complex() else B.inertia
+    neg, info = count(analysis, H, S, eps, L=L, work=work, stream=stream)
     for _ in range(max_retry):
         bad = np.nonzero(info)[0]
         if not len(bad):
             break
         scale = max(1.0, float(np.abs(eps).max()))
         eps[bad] += 1e-9 * scale
-        neg2, info2 = B.inertia(analysis, H, S, eps[bad], L=L, work=work, stream=stream)
+        neg2, info2 = count(analysis, H, S, eps[bad], L=L, work=work, stream=stream)
         neg[bad] = neg2
         info[bad] = info2
     if np.any(info):
@@ -138,10 +140,10 @@ def inertia_counts(analysis, H, S, eps, L=None, work=None, stream=None, max_retr
 
 def inertia_bracket(analysis, H, S, Ne, lo, hi, beta, Q=16, dN=0.1, rounds=3, tol=None, L=None, work=None,
                     stream=None, max_retry=4):
-    """Bracketing with N_inf from batched real LDL^T inertia counts on the
-    device."""
+    """Bracketing with N_inf from batched inertia counts on the device
+    (real LDL^T, or L D U for complex Hermitian H, S)."""
     if L is None or work is None:
-        L, work = analysis.buffers(Q, real=True, device=H.device)
+        L, work = _buffers(analysis, Q, H, real=True)
 
     def count(eps):
         return inertia_counts(analysis, H, S, eps, L=L, work=work, stream=stream, max_retry=max_retry)
@@ -216,18 +218,36 @@ def newton_from(evaluate, Ne, mu0, lo, hi, spectrum=(-1.0, 1.0), tol_ne=1e-8, ma
     return mu, N, dN, len(hist), lo, hi, hist, payload
 
 
+def _buffers(analysis, nshift, H, real=False):
+    """Factor storage and workspace for nshift shifts of the path H takes."""
+    if H.is_complex():
+        import torch
+        lb, wb = B.hermitian_sizes(analysis, nshift)
+        return (torch.empty(lb, dtype=torch.uint8, device=H.device),
+                torch.empty(wb, dtype=torch.uint8, device=H.device))
+    return analysis.buffers(nshift, real=real, device=H.device)
+
+
 def newton_mu(analysis, H, S, Ne, mu0, lo, hi, beta, P, spectrum=(-1.0, 1.0), tol_ne=1e-8, maxit=30,
               L=None, work=None, stream=None):
     """Newton for Tr[Gamma_P(mu) S] = Ne; every iterate is one density
-    matrix (weight sets rho, E, F, d) on the device.  spectrum bounds the
+    matrix (weight sets rho, E, F, d) on the device (for complex Hermitian
+    H, S through the L D U path, Gamma = (M - M^H)/2i).  spectrum bounds the
     pencil's eigenvalues; Delta E = max |bound - mu|."""
     if L is None or work is None:
-        L, work = analysis.buffers(P, device=H.device)
+        L, work = _buffers(analysis, P, H)
 
     def evaluate(mu):
         dE = max(abs(spectrum[0] - mu), abs(spectrum[1] - mu))
-        out, tr, info, _, _ = B.density_matrix(analysis, H, S, beta, dE, mu, P, nsets=4, L=L, work=work,
-                                               stream=stream)
+        if H.is_complex():
+            sh, wt = B.poles(beta, dE, mu, P, 4)
+            f = B.HermitianFactorization(analysis, H, S, sh, L=L, work=work, stream=stream)
+            info = f.info.copy()
+            f.selinv(stream=stream)
+            out, tr = f.pole_sum(wt, stream=stream)
+        else:
+            out, tr, info, _, _ = B.density_matrix(analysis, H, S, beta, dE, mu, P, nsets=4, L=L, work=work,
+                                                   stream=stream)
         if np.any(info):
             raise B.PxsError("newton_mu", B.PXS_TINY_PIVOT, f"tiny pivot at mu={mu}")
         return float(tr[0, 0]), float(tr[3, 0]), (out, tr)

@@ -380,6 +380,34 @@ pxs_status pxs_inertia(pxs_symbolic sym, const double* Hval, const double* Sval,
   return tiny ? PXS_TINY_PIVOT : PXS_OK;
 }
 
+pxs_status pxs_inertia_hermitian(pxs_symbolic sym, const pxs_c64* Hval, const pxs_c64* Sval, int32_t nshift,
+                                 const double* eps, void* Lbuf, void* work, int64_t* neg_count, int64_t* info,
+                                 void* stream) {
+  pxs_status s0 = check_numeric_args(sym, (const double*)Hval, (const double*)Sval, nshift, Lbuf, work);
+  if (s0 != PXS_OK) return s0;
+  if (!eps || !neg_count) return PXS_EINVAL;
+  std::vector<double> sh(2 * nshift, 0.0);
+  for (int32_t q = 0; q < nshift; ++q) {
+    if (!std::isfinite(eps[q])) return PXS_EINVAL;
+    sh[2 * q] = eps[q];
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int e = pxs::run_factor_h(sym->S, (const double*)Hval, (const double*)Sval, nshift, sh.data(), Lbuf, work, st);
+  if (e != 0) return hip_fail(e);
+  std::vector<int64_t> tmp(2 * pxs::MAX_SHIFTS);
+  hipError_t he = hipMemcpyAsync(tmp.data(), (char*)work + pxs::WK_INFO, sizeof(int64_t) * 2 * pxs::MAX_SHIFTS,
+                                 hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(he);
+  bool tiny = false;
+  for (int32_t q = 0; q < nshift; ++q) {
+    neg_count[q] = tmp[pxs::MAX_SHIFTS + q];
+    if (info) info[q] = tmp[q];
+    tiny = tiny || tmp[q] != 0;
+  }
+  return tiny ? PXS_TINY_PIVOT : PXS_OK;
+}
+
 pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double* Sval, double beta,
                               double dE, double mu, int32_t P, int32_t nsets, void* Lbuf, void* work,
                               double* out, double* traces, int64_t* info, pxs_c64* shifts,
