@@ -13,6 +13,9 @@
   one selected inversion, then pole sums with weight 2/pi on each energy's
   own shift (up to four energies per pass).  Tr[G(eps) S] is the
   Lorentzian-broadened DOS.
+Complex Hermitian pencils take the L D U path: counts from the signs of its
+real pivots at real shifts, and G(eps) = (2/pi) (M - M^H) / 2i with
+M = [H - (eps + i eta) S]^{-1}, which is the entrywise Im for real pencils.
 Host orchestration only: every factorization, selected inversion and sum
 runs in the library's kernels.
 """
@@ -21,7 +24,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import binding as B
-from .chempot import inertia_counts
+from .chempot import _buffers, inertia_counts
 
 
 def cdos(analysis, H, S, eps, batch=32, stream=None):
@@ -29,7 +32,7 @@ def cdos(analysis, H, S, eps, batch=32, stream=None):
     factorizations)."""
     eps = np.asarray(eps, dtype=np.float64)
     q = min(batch, max(1, len(eps)))
-    L, W = analysis.buffers(q, real=True, device=H.device)
+    L, W = _buffers(analysis, q, H, real=True)
     out = np.empty(len(eps), dtype=np.int64)
     for i in range(0, len(eps), q):
         out[i:i + q] = 2 * inertia_counts(analysis, H, S, eps[i:i + q], L=L, work=W, stream=stream)
@@ -48,18 +51,20 @@ def dos(analysis, H, S, edges, batch=32, stream=None):
 
 def ldos(analysis, H, S, energies, eta, stream=None):
     """G(eps_j) on the lower pattern for each energy; returns
-    (out: (m, nnz_lower) tensor, traces: (m, 2) with Tr[G S] and Tr[G H],
-    info)."""
+    (out: (m, nnz_lower) tensor, float64, complex128 for Hermitian input;
+    traces: (m, 2) with Tr[G S] and Tr[G H]; info)."""
     import torch
     energies = np.asarray(energies, dtype=np.float64)
     if eta <= 0:
         raise ValueError("eta must be positive")
     m = len(energies)
     shifts = energies + 1j * eta
-    f = B.Factorization(analysis, H, S, shifts, stream=stream)
+    herm = H.is_complex()
+    F = B.HermitianFactorization if herm else B.Factorization
+    f = F(analysis, H, S, shifts, stream=stream)
     f.selinv(stream=stream)
     nnz = analysis.info["nnz_lower"]
-    out = torch.empty((m, nnz), dtype=torch.float64, device=H.device)
+    out = torch.empty((m, nnz), dtype=torch.complex128 if herm else torch.float64, device=H.device)
     traces = np.zeros((m, 2))
     for g0 in range(0, m, 4):
         g1 = min(m, g0 + 4)

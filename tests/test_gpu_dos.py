@@ -81,3 +81,40 @@ def test_ldos_matches_oracle(torch_cuda, name, eta):
         assert abs(tr[j, 1] - trH) <= TOL * max(1.0, abs(trH))
     say("ldos worst entry error", worst)
     assert worst <= TOL
+
+
+def test_hermitian_dos_and_ldos(torch_cuda):
+    """A complex Hermitian pencil: DOS bins bit-exact from the signs of the
+    L D U pivots; LDOS (2/pi)(M - M^H)/2i, M = [H - (eps + i eta) S]^{-1},
+    against the oracle's Hermitian inverse route; Tr[G S] against the
+    broadened DOS."""
+    torch = torch_cuda
+    from oracle import hermitian as oherm
+    from paper_1405_0194_amd import binding as B
+    from paper_1405_0194_amd import dos as pdos
+    s = lattice.make_hermitian_system("honeycomb", (4, 3), 13, 3.0, 80)
+    Hd, Sd = s.dense()
+    ev = oherm.gen_eigh(Hd, Sd)[0]
+    edges = np.linspace(-1.0137, 1.0213, 41)
+    assert np.min(np.abs(edges[:, None] - ev[None, :])) > 1e-9
+    say(f"case: hermitian dos/ldos N={s.n}")
+    a = B.Analysis.from_system(s).bind()
+    H = torch.from_numpy(s.hval).cuda()
+    S = torch.from_numpy(s.sval).cuda()
+    centres, g, c = pdos.dos(a, H, S, edges, batch=16)
+    assert np.array_equal(c, 2 * np.searchsorted(ev, edges, side="left"))
+    assert np.array_equal(g, odos.dos_bins(ev, edges))
+    energies = np.array([-0.2, 0.013, 0.3])
+    eta = 3e-3
+    out, tr, info = pdos.ldos(a, H, S, energies, eta)
+    assert np.all(info == 0) and out.dtype == torch.complex128
+    out = out.cpu().numpy()
+    cols = s.entry_cols()
+    worst = 0.0
+    for j, e in enumerate(energies):
+        G = oherm.gamma_route_a(Hd, Sd, np.array([e + 1j * eta]), {"g": np.array([2.0 / np.pi])})["g"]
+        worst = max(worst, float(np.max(odense.entry_error(out[j], G[s.rowind, cols]))))
+        ref = odos.broadened_dos(ev, e, eta)[0]
+        assert abs(tr[j, 0] - ref) <= TOL * max(1.0, abs(ref)), (e, tr[j, 0], ref)
+    say("hermitian ldos worst entry error", worst)
+    assert worst <= TOL
