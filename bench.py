@@ -359,7 +359,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} (world size {world}) "
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} (world size {world}) "
               "is not supported (multi-GPU pole sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
 
