@@ -257,6 +257,14 @@ enum { PXS_PLAN_ACCUMULATE = 1 };
 pxs_status pxs_plan_create(pxs_symbolic sym, const double* Hval, const double* Sval,
                            int32_t nshift, int32_t nsets, void* Lbuf, void* work, double* out,
                            int32_t flags, pxs_plan* plan);
+/* The same for a complex Hermitian pencil (Hval, Sval, Lbuf, work as for
+ * pxs_factor_hermitian): captures the L D U, the two-sided selected inversion
+ * (on the capturing stream) and the pole sums Gamma^g = (M - M^H) / 2i;
+ * out is device complex nsets * nnz_lower.  flags must be 0.  Run, results
+ * and free as for pxs_plan_create. */
+pxs_status pxs_plan_create_hermitian(pxs_symbolic sym, const pxs_c64* Hval, const pxs_c64* Sval,
+                                     int32_t nshift, int32_t nsets, void* Lbuf, void* work, pxs_c64* out,
+                                     int32_t flags, pxs_plan* plan);
 pxs_status pxs_plan_run(pxs_plan plan, const pxs_c64* shifts, const pxs_c64* weights,
                         double* traces, int64_t* info, void* stream);
 /* Traces (host, 2 * nsets, nullable) and info (host, nshift, nullable) of

@@ -6,7 +6,9 @@ as the batch dimension of every launch.  Systems are admitted in decreasing
 order of work while their device footprint fits the memory budget, and are
 spread over several HIP streams so that small systems overlap with large
 ones (the paper's pole-level and system-level independence, Sec. II.B, taken
-to one device).  Host-side orchestration only: every numeric step runs in the
+to one device).  Complex Hermitian systems (k-points of a periodic system)
+run the L D U plan; those sharing a pattern may share one analysis.
+Host-side orchestration only: every numeric step runs in the
 library's kernels.
 """
 from __future__ import annotations
@@ -38,9 +40,25 @@ class Job:
     t_done: float = 0.0
 
 
-def footprint(analysis, P, nsets=2):
+def footprint(analysis, P, nsets=2, hermitian=False):
     i = analysis.info
+    if hermitian:
+        lb, wb = B.hermitian_sizes(analysis, P)
+        return lb + wb + 16 * nsets * i["nnz_lower"]
     return P * i["bytes_per_shift"] + analysis.workspace_size(P) + 8 * nsets * i["nnz_lower"]
+
+
+def _hermitian(job):
+    return np.iscomplexobj(job.system.hval)
+
+
+def _buffers(job, device):
+    import torch
+    if _hermitian(job):
+        lb, wb = B.hermitian_sizes(job.analysis, job.poles)
+        return (torch.empty(lb, dtype=torch.uint8, device=device),
+                torch.empty(wb, dtype=torch.uint8, device=device))
+    return job.analysis.buffers(job.poles, device=device)
 
 
 class BatchRunner:
@@ -64,8 +82,10 @@ class BatchRunner:
                 else:
                     j.analysis = B.Analysis.from_system(j.system)
             j.analysis.bind(device)
-            j.footprint = footprint(j.analysis, j.poles, j.nsets)
-            j.flops = j.poles * (j.analysis.info["flops_factor"] + j.analysis.info["flops_selinv"])
+            j.footprint = footprint(j.analysis, j.poles, j.nsets, _hermitian(j))
+            # L D U: full Schur complements and both triangles of SelInv
+            j.flops = (2.0 if _hermitian(j) else 1.0) * j.poles * (
+                j.analysis.info["flops_factor"] + j.analysis.info["flops_selinv"])
             if j.footprint > self.budget:
                 raise B.PxsError("BatchRunner", B.PXS_ENOMEM,
                                  f"job of {j.footprint / 2**30:.1f} GiB exceeds the budget")
@@ -98,7 +118,7 @@ class BatchRunner:
                 st = self.streams[si]
                 with torch.cuda.stream(st):
                     H, S = self._values(j)
-                    L, W = j.analysis.buffers(j.poles, device=self.device)
+                    L, W = _buffers(j, self.device)
                     plan = B.Plan(j.analysis, H, S, j.poles, nsets=j.nsets, L=L, work=W, device=self.device)
                     sh, wt = B.poles(j.beta, 1.0 + abs(j.mu), j.mu, j.poles, j.nsets)
                     j.t_submit = time.perf_counter()
@@ -118,7 +138,11 @@ class BatchRunner:
             j.t_done = time.perf_counter()
             j.traces, j.info = plan.results(stream=self.streams[si])
             if self.keep:
-                j.out = plan.out.view(j.nsets, -1).clone()
+                # copied on the job's stream: the buffers freed below go back
+                # to that stream's pool, so a later job on it cannot reuse
+                # them before the copy has read them
+                with torch.cuda.stream(self.streams[si]):
+                    j.out = plan.out.view(j.nsets, -1).clone()
             del plan, bufs
             used -= j.footprint
             free_streams.append(si)

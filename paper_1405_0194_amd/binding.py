@@ -80,6 +80,7 @@ def load():
         "pxs_density_matrix": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
                                          C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
         "pxs_plan_create": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P]),
+        "pxs_plan_create_hermitian": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P]),
         "pxs_plan_run": (C.c_int, [_P, _P, _P, _P, _P, _P]),
         "pxs_plan_results": (C.c_int, [_P, _P, _P, _P]),
         "pxs_plan_free": (None, [_P]),
@@ -395,25 +396,48 @@ class Plan:
 
     def __init__(self, analysis: Analysis, H, S, nshift, nsets=2, L=None, work=None, device="cuda",
                  out=None, accumulate=False):
+        """Complex H and S (complex128) capture the Hermitian path; out is
+        then complex."""
         import torch
         lib = load()
         self._lib = lib
         self.analysis = analysis.bind()
         self.nshift, self.nsets = int(nshift), int(nsets)
-        if L is None or work is None:
-            L, work = analysis.buffers(nshift)
-        _require_values(analysis, H, S)
-        _require(L, self.nshift * analysis.info["bytes_per_shift"], "factor storage")
-        _require(work, analysis.workspace_size(self.nshift), "workspace")
+        self.hermitian = H.is_complex()
+        nnz = analysis.info["nnz_lower"]
+        if self.hermitian:
+            lb, wb = hermitian_sizes(analysis, self.nshift)
+            if L is None or work is None:
+                L = torch.empty(lb, dtype=torch.uint8, device=H.device)
+                work = torch.empty(wb, dtype=torch.uint8, device=H.device)
+            for t, name in ((H, "H values"), (S, "S values")):
+                if t.dtype != torch.complex128 or t.numel() != nnz or not t.is_cuda or not t.is_contiguous():
+                    raise ValueError(f"{name}: need a contiguous complex128 device tensor of {nnz} entries")
+            _require(L, lb, "factor storage")
+            _require(work, wb, "workspace")
+        else:
+            if L is None or work is None:
+                L, work = analysis.buffers(nshift)
+            _require_values(analysis, H, S)
+            _require(L, self.nshift * analysis.info["bytes_per_shift"], "factor storage")
+            _require(work, analysis.workspace_size(self.nshift), "workspace")
         self.L, self.work, self.H, self.S = L, work, H, S
+        dt = torch.complex128 if self.hermitian else torch.float64
         if out is None:
-            out = torch.empty(nsets * analysis.info["nnz_lower"], dtype=torch.float64, device=L.device)
-        _require(out, 8 * nsets * analysis.info["nnz_lower"], "pole-sum output")
+            out = torch.empty(nsets * nnz, dtype=dt, device=L.device)
+        _require(out, (16 if self.hermitian else 8) * nsets * nnz, "pole-sum output")
         self.out = out
         h = _P()
-        _check("pxs_plan_create", lib.pxs_plan_create(analysis._h, _dptr(H), _dptr(S), self.nshift, self.nsets,
-                                                       _dptr(L), _dptr(work), _dptr(self.out),
-                                                       1 if accumulate else 0, C.byref(h)))
+        if self.hermitian:
+            if accumulate:
+                raise ValueError("accumulate is not available for Hermitian plans")
+            _check("pxs_plan_create_hermitian",
+                   lib.pxs_plan_create_hermitian(analysis._h, _dptr(H), _dptr(S), self.nshift, self.nsets,
+                                                 _dptr(L), _dptr(work), _dptr(self.out), 0, C.byref(h)))
+        else:
+            _check("pxs_plan_create", lib.pxs_plan_create(analysis._h, _dptr(H), _dptr(S), self.nshift,
+                                                           self.nsets, _dptr(L), _dptr(work), _dptr(self.out),
+                                                           1 if accumulate else 0, C.byref(h)))
         self._h = h
 
     def run(self, shifts, weights, stream=None, sync=True):

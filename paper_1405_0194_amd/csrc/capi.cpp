@@ -429,12 +429,15 @@ pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double
   return piv;
 }
 
-pxs_status pxs_plan_create(pxs_symbolic sym, const double* Hval, const double* Sval, int32_t nshift,
-                           int32_t nsets, void* Lbuf, void* work, double* out, int32_t flags,
-                           pxs_plan* plan) {
+// One capture for both kinds of pencil: herm selects the L D U kernels (no
+// accumulation into out for those).
+static pxs_status plan_create(pxs_symbolic sym, const double* Hval, const double* Sval, int32_t nshift,
+                              int32_t nsets, void* Lbuf, void* work, double* out, int32_t flags, bool herm,
+                              pxs_plan* plan) {
   pxs_status s0 = check_numeric_args(sym, Hval, Sval, nshift, Lbuf, work);
   if (s0 != PXS_OK) return s0;
   if (!out || !plan || nsets < 1 || nsets > 4 || (flags & ~PXS_PLAN_ACCUMULATE)) return PXS_EINVAL;
+  if (herm && (flags & PXS_PLAN_ACCUMULATE)) return PXS_EINVAL;
   *plan = nullptr;
   pxs_plan_s* p = new (std::nothrow) pxs_plan_s;
   if (!p) return PXS_ENOMEM;
@@ -454,11 +457,18 @@ pxs_status pxs_plan_create(pxs_symbolic sym, const double* Hval, const double* S
   if (k == 0) {
     k = (int)hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (k == 0) {
-      k = pxs::run_factor_kernels<true>(sym->S, Hval, Sval, nshift, Lbuf, work, cs);
-      if (k == 0) k = pxs::run_selinv(sym->S, nshift, Lbuf, work, cs, p->events.data());
-      if (k == 0)
-        k = pxs::run_pole_sum_kernels(sym->S, nshift, Lbuf, work, Hval, Sval, nsets, out,
-                                      (flags & PXS_PLAN_ACCUMULATE) ? 1 : 0, cs);
+      if (herm) {
+        // inside a capture the Hermitian SelInv stays on the capturing stream
+        k = pxs::run_factor_kernels_h(sym->S, Hval, Sval, nshift, Lbuf, work, cs);
+        if (k == 0) k = pxs::run_selinv_h(sym->S, nshift, Lbuf, work, cs);
+        if (k == 0) k = pxs::run_pole_sum_kernels_h(sym->S, nshift, Lbuf, work, Hval, Sval, nsets, out, cs);
+      } else {
+        k = pxs::run_factor_kernels<true>(sym->S, Hval, Sval, nshift, Lbuf, work, cs);
+        if (k == 0) k = pxs::run_selinv(sym->S, nshift, Lbuf, work, cs, p->events.data());
+        if (k == 0)
+          k = pxs::run_pole_sum_kernels(sym->S, nshift, Lbuf, work, Hval, Sval, nsets, out,
+                                        (flags & PXS_PLAN_ACCUMULATE) ? 1 : 0, cs);
+      }
       hipGraph_t g = nullptr;
       const hipError_t e2 = hipStreamEndCapture(cs, &g);
       if (e2 == hipSuccess) p->graph = g;   // only a graph the capture produced is kept
@@ -473,6 +483,19 @@ pxs_status pxs_plan_create(pxs_symbolic sym, const double* Hval, const double* S
   }
   *plan = p;
   return PXS_OK;
+}
+
+pxs_status pxs_plan_create(pxs_symbolic sym, const double* Hval, const double* Sval, int32_t nshift,
+                           int32_t nsets, void* Lbuf, void* work, double* out, int32_t flags,
+                           pxs_plan* plan) {
+  return plan_create(sym, Hval, Sval, nshift, nsets, Lbuf, work, out, flags, false, plan);
+}
+
+pxs_status pxs_plan_create_hermitian(pxs_symbolic sym, const pxs_c64* Hval, const pxs_c64* Sval, int32_t nshift,
+                                     int32_t nsets, void* Lbuf, void* work, pxs_c64* out, int32_t flags,
+                                     pxs_plan* plan) {
+  return plan_create(sym, (const double*)Hval, (const double*)Sval, nshift, nsets, Lbuf, work, (double*)out,
+                     flags, true, plan);
 }
 
 pxs_status pxs_plan_run(pxs_plan plan, const pxs_c64* shifts, const pxs_c64* weights, double* traces,

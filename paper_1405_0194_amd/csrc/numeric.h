@@ -60,7 +60,11 @@ int64_t herm_storage_bytes(const Symbolic& S, int nshift);
 int64_t herm_work_bytes(const Symbolic& S, int nshift);
 int run_factor_h(const Symbolic& S, const double* H, const double* Sv, int nshift, const double* shifts_host,
                  void* L, void* work, hipStream_t st);
+int run_factor_kernels_h(const Symbolic& S, const double* H, const double* Sv, int nshift, void* L, void* work,
+                         hipStream_t st);
 int run_selinv_h(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st);
+int run_pole_sum_kernels_h(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
+                           const double* Sv, int nsets, double* out, hipStream_t st);
 int run_pole_sum_h(const Symbolic& S, int nshift, const void* L, void* work, const double* H, const double* Sv,
                    int nsets, const double* weights_host, double* out, hipStream_t st);
 int run_gather_h(const Symbolic& S, int shift, bool upper, const void* L, void* out, hipStream_t st);

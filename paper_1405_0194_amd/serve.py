@@ -229,7 +229,13 @@ class Server:
         if req.traces is None:
             req.traces, req.info = r.plan(req.poles, False).results(stream=self.streams[si])
         if self.keep:
-            req.out = r.out.view(req.nsets, -1).clone()
+            # the resident output is rewritten by the next request on this
+            # resident, possibly on another stream: copy it on this request's
+            # stream and wait for the copy before releasing the resident
+            st = self.streams[si]
+            with self.torch.cuda.stream(st):
+                req.out = r.out.view(req.nsets, -1).clone()
+            st.synchronize()
         r.busy = False
 
     def run(self, requests, realtime=True):
