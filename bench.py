@@ -140,6 +140,25 @@ def cpu_baseline(full_n, seconds_target=15.0):
                        f"scaled by (N_sample/N)^3 to N={full_n}")}
 
 
+def cpu_eigh_baseline(full_n, reps=2):
+    """The dense-diagonalization route the method replaces: the oracle's
+    generalized eigendecomposition of (H, S) (one per density matrix, any P),
+    timed on a smaller honeycomb sample and scaled by (N / N_sample)^3."""
+    from oracle import dense
+    from paper_1405_0194_amd import lattice
+    cells = 10
+    s = lattice.make_system("honeycomb", (cells, cells), 13, 3.0, 7)
+    Hd, Sd = s.dense()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dense.gen_eigh(Hd, Sd)
+    per = (time.perf_counter() - t0) / reps
+    return {"seconds_per_density_matrix": round(per * (float(full_n) / s.n) ** 3, 1), "kind": "oracle",
+            "sample": (f"{reps} generalized dense eigendecompositions (scipy eigh) of a honeycomb {cells}x{cells}x2 "
+                       f"atoms x 13 orbitals pencil (N={s.n}), {per:.2f} s each, scaled by (N/N_sample)^3 to "
+                       f"N={full_n}; the GPU path takes ms_per_step for one density matrix")}
+
+
 def per_pole_sample(a, H, S, beta, dE, mu, P, nsample):
     """The plain per-pole loop (same kernels, one shift per factorization,
     no batching, no graphs) on the first nsample shifts: seconds per shift."""
@@ -575,6 +594,7 @@ def main():
         del L, W
         torch.cuda.empty_cache()
         res["cpu_baseline"] = cpu_baseline(s.n)
+        res["cpu_eigh"] = cpu_eigh_baseline(s.n)
     print(json.dumps(res), flush=True)
 
 
