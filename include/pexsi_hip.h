@@ -15,7 +15,13 @@
  *       of H and S (eqs. gammapole, gammaF) and the traces Tr(Gamma^g S),
  *       Tr(Gamma^g H) (eq. Nmu),
  *     - inertia counts #{negative d_k} of H - eps S in real arithmetic
- *       (Sec. II.C, Sylvester's law of inertia).
+ *       (Sec. II.C, Sylvester's law of inertia);
+ *   for a complex Hermitian pencil (S Hermitian positive definite; the
+ *   variant the paper's conclusion names for k-point sampling) the same
+ *   steps with an L D U factorization, two-sided selected inversion, the
+ *   density matrix as the matrix imaginary part (M - M^H) / 2i of the pole
+ *   sum M, and inertia from the real pivots at real shifts (the *_hermitian
+ *   functions).
  *
  * Conventions
  *   - Every function returns a pxs_status; nothing throws across the ABI.
@@ -35,6 +41,12 @@
  *     is a host array (traces, counts, info), which synchronises the stream.
  *   - Complex numbers are pxs_c64 {re, im}, layout-compatible with C99
  *     double complex and numpy/torch complex128.
+ *   - Threads: a bound symbolic handle is read-only and may serve calls on
+ *     several streams.  Eager selected inversion with more than one stream
+ *     (pxs_selinv, pxs_density_matrix) runs independent subtrees on a
+ *     process-wide pool of streams and events per device: issue such calls
+ *     from one host thread at a time.  Graph plans use only the stream
+ *     passed to pxs_plan_run.
  */
 #ifndef PEXSI_HIP_H
 #define PEXSI_HIP_H
