@@ -188,7 +188,9 @@ pxs_status pxs_factor(pxs_symbolic sym, const double* Hval, const double* Sval,
  * works with pxs_selinv (selected inverse of both triangles), pxs_pole_sum
  * (complex output, see there), pxs_get_selected (lower triangle Z_l[i][j],
  * i >= j), pxs_get_selected_upper (Z_l[j][i] at the same entries) and
- * pxs_get_diag.  SelInv of a Hermitian handle runs on the given stream only.
+ * pxs_get_diag.  SelInv of a Hermitian handle runs independent subtrees on
+ * the library's streams as for real pencils (one stream inside a capture);
+ * selinv_chunk does not apply: the workspace covers the whole batch.
  * Errors and info as for pxs_factor. */
 pxs_status pxs_hermitian_sizes(pxs_symbolic sym, int32_t nshift, int64_t* lbuf_bytes, int64_t* work_bytes);
 pxs_status pxs_factor_hermitian(pxs_symbolic sym, const pxs_c64* Hval, const pxs_c64* Sval,
