@@ -18,6 +18,13 @@ Modules
             inertia counts (eqs. gammaeq, gammapole, gammaF, Nmu; Sec. II.C).
   symbolic  brute-force boolean elimination: the pattern of L and the
             elimination tree by its definition (eq. parent).
+  chempot   the chemical-potential search of Sec. II.C (N_beta from inertia
+            samples, band-edge bracketing, the exact root of N_P(mu) = N_e).
+  dos       DOS bin averages and the LDOS (2/pi) Im [H - (eps + i eta) S]^{-1}
+            (Sec. II.D).
+  hermitian complex Hermitian pencils: Gamma as (M - M^H)/2i (conclusion).
+  sparse    single columns of A^{-1} by a Krylov solve, for systems too large
+            for the dense routes.
 
 Every function here is pinned by tests/test_oracle_*.py against closed forms,
 special cases, brute force or invariants -- see those files.

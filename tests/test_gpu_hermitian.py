@@ -201,6 +201,24 @@ def test_hermitian_full_size_bench_configuration(torch_cuda):
         r = _herm_identity_residual(s, sh[l], zl, zu)
         say("shift", l, "Im w", sh[l].imag, "diag(AZ)-1 residual", r)
         assert r <= 1e-11
+    # sampled entries one by one against the oracle's Krylov columns
+    from oracle import sparse as osparse
+    rows = s.rowind.astype(np.int64)
+    cols = s.entry_cols()
+    worst = 0.0
+    for l in (int(order[-1]), int(order[P * 3 // 4])):
+        A = osparse.matrix(s.n, s.colptr, s.rowind, s.hval, s.sval, sh[l])
+        zl = f.selected(l).cpu().numpy()
+        zu = f.selected(l, upper=True).cpu().numpy()
+        for j in (1234, s.n - 77):
+            x = osparse.inverse_column(A, j)
+            incol = np.nonzero(cols == j)[0]              # Z[i][j], i >= j
+            inrow = np.nonzero((rows == j) & (cols < j))[0]   # entry (j, k): Z[k][j] is the upper value
+            got = np.concatenate([zl[incol], zu[inrow]])
+            want = np.concatenate([x[rows[incol]], x[cols[inrow]]])
+            worst = max(worst, float(np.max(odense.entry_error(got, want))))
+    say("sampled columns worst entry error", worst)
+    assert worst <= TOL
     out, tr = f.pole_sum(wt)
     e_rho = opoles.expansion_error(BETA, dE, mu, P)
     e_E = opoles.expansion_error(BETA, dE, mu, P, g="E")

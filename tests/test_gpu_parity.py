@@ -305,6 +305,13 @@ def _full_size_check(torch, cfg, **akw):
         r = _diag_identity_residual(s, sh[l], z)
         say("shift", l, "Im w", sh[l].imag, "diag(AZ)-1 residual", r)
         assert r <= 1e-11
+    # sampled entries one by one: columns of A^{-1} from the oracle's Krylov
+    # solve, against the selected inverse on the column's and the row's
+    # input entries (shifts far from and nearer to the real axis)
+    worst = _sampled_columns_error(f, s, sh, [int(order[-1]), int(order[P * 3 // 4])],
+                                   [1234 % s.n, s.n - 77])
+    say("sampled columns worst entry error", worst)
+    assert worst <= TOL
     out, tr = f.pole_sum(wt)
     e_rho = opoles.expansion_error(BETA, dE, mu, P)
     e_E = opoles.expansion_error(BETA, dE, mu, P, g="E")
@@ -314,6 +321,30 @@ def _full_size_check(torch, cfg, **akw):
     assert 0.0 < tr[0, 0] < 2.0 * s.n
     del f, H, S
     torch.cuda.empty_cache()
+
+
+def _sampled_columns_error(f, s, sh, shifts, cols_j, upper=None):
+    """Worst per-entry error of Z_l[:, j] on the input pattern against the
+    oracle's column A_l^{-1} e_j: entries (i, j), i >= j, from the lower
+    extraction; entries (j, k), k < j, hold Z[j][k], which equals Z[k][j]
+    for complex symmetric A (or comes from the upper extraction, given as
+    upper(l), for Hermitian A)."""
+    from oracle import sparse as osparse
+    cols = s.entry_cols()
+    rows = s.rowind.astype(np.int64)
+    worst = 0.0
+    for l in shifts:
+        A = osparse.matrix(s.n, s.colptr, s.rowind, s.hval, s.sval, sh[l])
+        zl = f.selected(int(l)).cpu().numpy()
+        zu = upper(int(l)) if upper is not None else zl
+        for j in cols_j:
+            x = osparse.inverse_column(A, j)
+            incol = np.nonzero(cols == j)[0]
+            inrow = np.nonzero((rows == j) & (cols < j))[0]
+            got = np.concatenate([zl[incol], zu[inrow]])
+            want = np.concatenate([x[rows[incol]], x[cols[inrow]]])
+            worst = max(worst, float(np.max(odense.entry_error(got, want))))
+    return worst
 
 
 def test_full_size_honeycomb_bench_configuration(torch_cuda):

@@ -129,3 +129,23 @@ def test_entry_error_floor():
     x = y + np.array([1e-12, 1e-12, 0.0])
     err = dense.entry_error(x, y)
     assert err[1] == pytest.approx(1e-12 / 1e-3)
+
+
+@pytest.mark.parametrize("kind,dims,orb,cut,herm", [("honeycomb", (4, 3), 5, 3.0, False),
+                                                    ("cubic", (3, 3, 3), 4, 2.0, False),
+                                                    ("honeycomb", (4, 3), 5, 3.0, True)])
+def test_sparse_inverse_column_equals_dense_inverse(kind, dims, orb, cut, herm):
+    """The Krylov column of A^{-1} (used at sizes the dense routes cannot
+    reach) against the dense LU inverse, for a shift far from and one near
+    the real axis."""
+    from oracle import sparse
+    mk = lattice.make_hermitian_system if herm else lattice.make_system
+    s = mk(kind, dims, orb, cut, 17)
+    H, S = s.dense()
+    for w in (0.1 + 0.5j, -0.05 + 0.04j):
+        A = sparse.matrix(s.n, s.colptr, s.rowind, s.hval, s.sval, w)
+        assert np.abs(A.toarray() - (H - w * S)).max() == 0.0
+        Z = dense.shifted_inverse(H, S, w)
+        for j in (0, s.n // 2, s.n - 1):
+            x = sparse.inverse_column(A, j)
+            assert np.max(np.abs(x - Z[:, j])) <= 1e-12 * np.max(np.abs(Z[:, j]))
