@@ -198,6 +198,56 @@ __device__ __forceinline__ void acc_foreach(const Acc<CPLX, NTILE>& acc, F f) {
       }
 }
 
+// The idx-th accumulator element of the calling thread (the order in which
+// acc_foreach visits them) and its tile coordinates.
+template <int NTILE>
+constexpr int acc_elems() { return Geo<NTILE>::BM * Geo<NTILE>::BN * 4; }
+
+template <bool CPLX, int NTILE>
+__device__ __forceinline__ void acc_at(const Acc<CPLX, NTILE>& acc, int idx, int& m, int& n, cplx& v) {
+  using G = Geo<NTILE>;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int wm = (w / G::WN) * (G::BM * 16), wn = (w % G::WN) * 32;
+  const int r = idx & 3, b = (idx >> 2) % G::BN, a = (idx >> 2) / G::BN;
+  m = wm + a * 16 + (lane >> 4) + 4 * r;
+  n = wn + b * 16 + (lane & 15);
+  v = cplx{acc.re[a][b][r], CPLX ? acc.im[a][b][r] : 0.0};
+}
+
+// target[e] -= P for every accumulator element, in three passes so that a
+// thread's memory operations overlap instead of running one element at a
+// time: all target positions (addr(m, n, e) may read index maps; false
+// skips the element, whose e must still be an in-bounds position of
+// target), then all old values, then all stores.  Every target
+// belongs to one element of one workgroup, so reordering the stores changes
+// no result.
+template <bool CPLX, int NTILE, class AF>
+__device__ __forceinline__ void acc_sub_into(const Acc<CPLX, NTILE>& acc, double* target, AF addr) {
+  constexpr int NE = acc_elems<NTILE>();
+  int64_t e[NE];
+  bool ok[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    int m, n;
+    cplx v;
+    acc_at<CPLX, NTILE>(acc, i, m, n, v);
+    ok[i] = addr(m, n, e[i]);
+  }
+  // addr returns an in-bounds position also for skipped elements, so the
+  // old values load without branches
+  cplx o[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) o[i] = ld_elem<CPLX>(target, e[i]);
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    int m, n;
+    cplx v;
+    acc_at<CPLX, NTILE>(acc, i, m, n, v);
+    if (ok[i]) st_elem<CPLX>(target, e[i], cplx{o[i].re - v.re, o[i].im - v.im});
+  }
+}
+
 // Staging of one k-chunk of an operand with ROWS rows (64 or NTILE).
 // slot(j) gives the (row, k) pair thread t moves in its j-th transfer:
 // FAST_K = false puts consecutive threads on consecutive rows (memory
@@ -672,15 +722,11 @@ __global__ void PXS_LB(TN) k_int_update(Common c, PanelK p) {
         if (kg >= p.p0) return cplx{0.0, 0.0};
         return ld_elem<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg);
       });
-  acc_foreach<CPLX, TN>(acc, [&](int m, int n, cplx v) {
+  acc_sub_into<CPLX, TN>(acc, Ls, [&](int m, int n, int64_t& e) {
     const int rg = r0 + n;
-    if (m < p.wp && rg < nrows && rg >= m) {
-      const int64_t e = cbase + (int64_t)(p.p0 + m) * p.ld + rg;
-      cplx o = ld_elem<CPLX>(Ls, e);
-      o.re -= v.re;
-      o.im -= v.im;
-      st_elem<CPLX>(Ls, e, o);
-    }
+    // clamped into the panel (in bounds for skipped elements)
+    e = cbase + (int64_t)(p.p0 + min(m, p.wp - 1)) * p.ld + min(rg, nrows - 1);
+    return m < p.wp && rg < nrows && rg >= m;
   });
 }
 
@@ -735,16 +781,15 @@ __global__ void PXS_LB(TN) k_update(Common c, PanelK p) {
       });
   const int64_t* cmap = c.colmap + p.cm;
   const int64_t* cseg = c.colseg + p.cm;
-  acc_foreach<CPLX, TN>(acc, [&](int m, int n, cplx v) {
+  acc_sub_into<CPLX, TN>(acc, Ls, [&](int m, int n, int64_t& e) {
     const int jg = j0 + m, ig = i0 + n;
-    if (jg < p.nb && ig < p.nb && ig >= jg) {
-      const int qj = base + jg, qi = base + ig;
-      const int64_t e = cmap[qj] + c.relpos[cseg[qj] + qi];
-      cplx o = ld_elem<CPLX>(Ls, e);
-      o.re -= v.re;
-      o.im -= v.im;
-      st_elem<CPLX>(Ls, e, o);
-    }
+    // branch-free, so the map loads of all elements are in flight together:
+    // indices clamped into the supernode's row list with row >= column
+    // (where relpos is defined); a skipped element reads a valid position
+    // and is not stored
+    const int jc = min(jg, p.nb - 1), ic = min(max(ig, jc), p.nb - 1);
+    e = cmap[base + jc] + c.relpos[cseg[base + jc] + base + ic];
+    return jg < p.nb && ig < p.nb && ig >= jg;
   });
 }
 
