@@ -893,16 +893,19 @@ __global__ void __launch_bounds__(NT) k_gather_cc(Common c, PanelK p) {
   const int a = a0 + (t & 63);
   int64_t e[16];
   bool ok[16];
+  // branch-free, so all map and value loads of a thread are in flight
+  // together: indices clamped into Z_CC with row >= column (where relpos is
+  // defined); skipped elements read a valid position and are not stored
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int b = b0 + (t >> 6) + 4 * j;
     ok[j] = (a < cc && b < cc && a >= b);
-    e[j] = 0;
-    if (ok[j]) e[j] = cmap[w + b] + c.relpos[cseg[w + b] + w + a];
+    const int bc = min(b, cc - 1), ac = min(max(a, bc), cc - 1);
+    e[j] = cmap[w + bc] + c.relpos[cseg[w + bc] + w + ac];
   }
   cplx v[16];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = ok[j] ? ld_elem<true>(Ls, e[j]) : cplx{0.0, 0.0};
+  for (int j = 0; j < 16; ++j) v[j] = ld_elem<true>(Ls, e[j]);
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int b = b0 + (t >> 6) + 4 * j;
