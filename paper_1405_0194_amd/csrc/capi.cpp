@@ -476,7 +476,7 @@ static pxs_status plan_create(pxs_symbolic sym, const double* Hval, const double
     }
   }
   if (k == 0) k = (int)hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
-  if (cs) hipStreamDestroy(cs);
+  if (cs) (void)hipStreamDestroy(cs);   // cleanup: the capture's status decides
   if (k != 0) {
     pxs_plan_free(p);
     return hip_fail(k);
@@ -537,8 +537,8 @@ pxs_status pxs_plan_results(pxs_plan plan, double* traces, int64_t* info, void* 
 
 void pxs_plan_free(pxs_plan plan) {
   if (!plan) return;
-  if (plan->exec) hipGraphExecDestroy(plan->exec);
-  if (plan->graph) hipGraphDestroy(plan->graph);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
   for (hipEvent_t e : plan->events) hipEventDestroy(e);
   delete plan;
 }

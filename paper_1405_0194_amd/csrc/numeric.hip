@@ -944,10 +944,15 @@ __global__ void PXS_LB(64) k_selinv_diag_partial(Common c, PanelK p) {
 }
 
 // Z_pp = Linv^T D^{-1} Linv - sum of the partials, written over the diagonal block.
-__global__ void __launch_bounds__(NT) k_selinv_diag_final(Common c, PanelK p) {
+// One workgroup per shift (the block is overwritten in place, so it is read
+// by the same workgroup that writes it) with 1024 threads: a wave holds one
+// column cc and its 64 rows, so the work per wave follows the triangle.
+constexpr int NTF = 1024;
+__global__ void __launch_bounds__(NTF) k_selinv_diag_final(Common c, PanelK p) {
   __shared__ double l_re[64][LDP];   // l[col][row] = Linv[row][col]
   __shared__ double l_im[64][LDP];
   __shared__ cplx dinv[64];
+  constexpr int NE = 64 * 64 / NTF;
   const int sh = p.sh0 + blockIdx.y;
   double* Ls = shift_base<true>(c, sh);
   const double* W = wbase(c, sh);
@@ -955,21 +960,33 @@ __global__ void __launch_bounds__(NT) k_selinv_diag_final(Common c, PanelK p) {
   const int wp = p.wp;
   const int t = threadIdx.x;
   const int64_t dbase = p.off + (int64_t)p.p0 * p.ld + p.p0;
-  for (int idx = t; idx < wp * wp; idx += NT) {
-    const int cc = idx / wp, r = idx % wp;
-    cplx v{0.0, 0.0};
-    if (r > cc) v = ld_elem<true>(Ls, dbase + (int64_t)cc * p.ld + r);
-    if (r == cc) {
-      v = cplx{1.0, 0.0};
-      dinv[r] = cinv(ld_elem<true>(Ls, dbase + (int64_t)cc * p.ld + r));
+  // element (r, cc) of the block at slot u: cc = t / 64 + 16 u, r = t % 64;
+  // every load is issued before the first LDS store
+  const int r = t & 63, c0 = t >> 6;
+  cplx v[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int cc = c0 + u * (NTF / 64);
+    v[u] = cplx{0.0, 0.0};
+    if (cc < wp && r < wp && r >= cc) v[u] = ld_elem<true>(Ls, dbase + (int64_t)cc * p.ld + r);
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int cc = c0 + u * (NTF / 64);
+    cplx x = (r > cc) ? v[u] : cplx{0.0, 0.0};
+    if (r == cc && r < wp) {
+      x = cplx{1.0, 0.0};
+      dinv[r] = cinv(v[u]);
     }
-    l_re[cc][r] = v.re;
-    l_im[cc][r] = v.im;
+    l_re[cc][r] = x.re;
+    l_im[cc][r] = x.im;
   }
   __syncthreads();
   const int nsplit = (p.nb > 0) ? p.split : 0;
-  for (int idx = t; idx < wp * wp; idx += NT) {
-    const int cc = idx / wp, r = idx % wp;   // element (r, cc)
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int cc = c0 + u * (NTF / 64);
+    if (cc >= wp || r >= wp) continue;
     // sum_{k >= max(r, cc)} Linv[k][r] dinv[k] Linv[k][cc]
     cplx s{0.0, 0.0};
     for (int k = max(r, cc); k < wp; ++k) {
@@ -1078,8 +1095,9 @@ struct ProfScope {
   hipStream_t st;
   bool on;
   int err = 0;
+  double w_, b_;
   ProfScope(int kernel, hipStream_t s, double work, double bytes)
-      : st(s), on(g_prof.kernel == kernel && kernel != KC_NONE) {
+      : st(s), on(g_prof.kernel == kernel && kernel != KC_NONE), w_(work), b_(bytes) {
     if (!on) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
@@ -1091,15 +1109,16 @@ struct ProfScope {
       if (hipEventCreate(&e) != hipSuccess) { on = false; err = 1; return; }
       g_prof.ev.push_back(e);
     }
-    hipEventRecord(g_prof.ev[g_prof.used], st);
-    g_prof.launches += 1;
-    g_prof.work += work;
-    g_prof.bytes += bytes;
+    if (hipEventRecord(g_prof.ev[g_prof.used], st) != hipSuccess) { on = false; err = 1; }
   }
   ~ProfScope() {
     if (!on) return;
-    hipEventRecord(g_prof.ev[g_prof.used + 1], st);
+    // a launch counts only with both of its events recorded
+    if (hipEventRecord(g_prof.ev[g_prof.used + 1], st) != hipSuccess) return;
     g_prof.used += 2;
+    g_prof.launches += 1;
+    g_prof.work += w_;
+    g_prof.bytes += b_;
   }
 };
 
@@ -1440,7 +1459,7 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
             hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, nsh), dim3(NT), 0, sj, c, k);
           }
         }
-        hipLaunchKernelGGL(k_selinv_diag_final, dim3(1, nsh), dim3(NT), 0, sj, c, k);
+        hipLaunchKernelGGL(k_selinv_diag_final, dim3(1, nsh), dim3(NTF), 0, sj, c, k);
         PXS_CHECK_LAUNCH();
       }
       if (!single && S.cross_child[J]) PXS_HIP(hipEventRecord(ev[J], sj));
