@@ -913,7 +913,7 @@ __global__ void __launch_bounds__(NT) k_gather_cc(Common c, PanelK p) {
   }
 }
 
-// Partial W^T Z_Bp over k in [split * 512, ...): P[c][r] = sum_k Z[k][c] W[k][r].
+// Partial W^T Z_Bp over k in [split * SPLIT_ROWS, ...): P[c][r] = sum_k Z[k][c] W[k][r].
 __global__ void PXS_LB(64) k_selinv_diag_partial(Common c, PanelK p) {
   __shared__ Stage2<true, TM> s;
   int bx, by;
@@ -925,7 +925,7 @@ __global__ void PXS_LB(64) k_selinv_diag_partial(Common c, PanelK p) {
   double* part = W + 2 * (int64_t)p.nb * p.wp;   // after W: split x 64 x 64 complex
   const int base = p.p0 + p.wp;
   const int64_t rbase = p.off + (int64_t)p.p0 * p.ld + base;
-  const int kb = sp * 512, ke = min(p.nb, kb + 512);
+  const int kb = sp * (int)SPLIT_ROWS, ke = min(p.nb, kb + (int)SPLIT_ROWS);
   Acc<true, TM> acc;
   acc.zero();
   gemm_pipe<true, TM, true>(

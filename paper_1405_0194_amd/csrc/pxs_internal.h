@@ -96,11 +96,11 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
             const int32_t* blkptr, const double* coords, const AnalyzeOptions& opt,
             Symbolic& S, std::string& msg);
 
-// Number of split-K pieces used by the diagonal-block SelInv update of a panel
-// with `below` rows beneath it.
+// Rows of one split-K piece of the diagonal-block SelInv update, and the
+// number of pieces for a panel with `below` rows beneath it.
+constexpr int64_t SPLIT_ROWS = 256;
 inline int32_t split_count(int64_t below) {
-  const int64_t chunk = 512;
-  int64_t s = (below + chunk - 1) / chunk;
+  int64_t s = (below + SPLIT_ROWS - 1) / SPLIT_ROWS;
   if (s < 1) s = 1;
   return (int32_t)s;
 }
