@@ -298,7 +298,9 @@ void pxs_plan_free(pxs_plan plan);
  * padding; for kernels 7, 8 and 9 their algorithmic HBM bytes instead) and, in
  * `bytes` (nullable), their algorithmic HBM bytes: every operand read once
  * and every result written once.
- * Process-wide state; not thread safe.  PXS_ESTATE if no profile is open. */
+ * Process-wide state; not thread safe.  PXS_ESTATE if no profile is open;
+ * PXS_EHIP (and no totals) if an event could not be created or recorded
+ * during the profile. */
 pxs_status pxs_profile_begin(int32_t kernel);
 pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work, double* bytes);
 

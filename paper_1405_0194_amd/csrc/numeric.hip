@@ -1088,13 +1088,13 @@ struct Profiler {
   int64_t launches = 0;
   double work = 0.0;    // algorithmic flops (bytes for the memory-bound classes)
   double bytes = 0.0;   // algorithmic HBM bytes: operands read once, results written once
+  int failed = 0;       // HIP error of an event create/record inside the profile, 0 if none
 };
 Profiler g_prof;
 
 struct ProfScope {
   hipStream_t st;
   bool on;
-  int err = 0;
   double w_, b_;
   ProfScope(int kernel, hipStream_t s, double work, double bytes)
       : st(s), on(g_prof.kernel == kernel && kernel != KC_NONE), w_(work), b_(bytes) {
@@ -1106,15 +1106,21 @@ struct ProfScope {
     }
     while (g_prof.ev.size() < g_prof.used + 2) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) { on = false; err = 1; return; }
+      const hipError_t ce = hipEventCreate(&e);
+      if (ce != hipSuccess) { on = false; g_prof.failed = (int)ce; return; }
       g_prof.ev.push_back(e);
     }
-    if (hipEventRecord(g_prof.ev[g_prof.used], st) != hipSuccess) { on = false; err = 1; }
+    const hipError_t re = hipEventRecord(g_prof.ev[g_prof.used], st);
+    if (re != hipSuccess) { on = false; g_prof.failed = (int)re; }
   }
   ~ProfScope() {
     if (!on) return;
     // a launch counts only with both of its events recorded
-    if (hipEventRecord(g_prof.ev[g_prof.used + 1], st) != hipSuccess) return;
+    const hipError_t re = hipEventRecord(g_prof.ev[g_prof.used + 1], st);
+    if (re != hipSuccess) {
+      g_prof.failed = (int)re;
+      return;
+    }
     g_prof.used += 2;
     g_prof.launches += 1;
     g_prof.work += w_;
@@ -1182,11 +1188,18 @@ int profile_begin(int kernel) {
   g_prof.launches = 0;
   g_prof.work = 0.0;
   g_prof.bytes = 0.0;
+  g_prof.failed = 0;
   return 0;
 }
 
 int profile_end(double* ms, int64_t* launches, double* work, double* bytes) {
   if (g_prof.kernel == KC_NONE) return -1;   // no profile open
+  if (g_prof.failed) {                        // totals would be partial
+    const int f = g_prof.failed;
+    g_prof.kernel = KC_NONE;
+    g_prof.used = 0;
+    return f;
+  }
   double tot = 0.0;
   for (size_t i = 0; i + 1 < g_prof.used; i += 2) {
     hipError_t e = hipEventSynchronize(g_prof.ev[i + 1]);
