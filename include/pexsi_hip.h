@@ -42,11 +42,13 @@
  *   - Complex numbers are pxs_c64 {re, im}, layout-compatible with C99
  *     double complex and numpy/torch complex128.
  *   - Threads: a bound symbolic handle is read-only and may serve calls on
- *     several streams.  Eager selected inversion with more than one stream
- *     (pxs_selinv, pxs_density_matrix) runs independent subtrees on a
- *     process-wide pool of streams and events per device: issue such calls
- *     from one host thread at a time.  Graph plans use only the stream
- *     passed to pxs_plan_run.
+ *     several streams.  Eager factorization and selected inversion with more
+ *     than one subtree stream (pxs_factor, pxs_inertia, pxs_selinv,
+ *     pxs_density_matrix; the real and complex-symmetric paths) run
+ *     independent subtrees on a process-wide pool of streams and events per
+ *     device: issue such calls from one host thread at a time.  The results
+ *     do not depend on the number of streams (bit-identical).  Graph plans
+ *     use only the stream passed to pxs_plan_run.
  */
 #ifndef PEXSI_HIP_H
 #define PEXSI_HIP_H

@@ -638,8 +638,17 @@ __global__ void __launch_bounds__(NTD) k_diag(Common c, PanelK p) {
     __syncthreads();
   }
   if (t == 0) {
-    // panels run in column order, so the first flagged column wins
-    if (bad) atomicCAS((unsigned long long*)&c.info[sh], 0ull, (unsigned long long)bad);
+    // the smallest flagged column wins (0 = none yet), whatever the order in
+    // which independent subtrees run
+    if (bad) {
+      unsigned long long* q = (unsigned long long*)&c.info[sh];
+      unsigned long long old = atomicCAS(q, 0ull, (unsigned long long)bad);
+      while (old != 0ull && old > (unsigned long long)bad) {
+        const unsigned long long seen = atomicCAS(q, old, (unsigned long long)bad);
+        if (seen == old) break;
+        old = seen;
+      }
+    }
     if (!CPLX && neg) atomicAdd((unsigned long long*)&c.negc[sh], (unsigned long long)neg);
   }
   for (int idx = t; idx < wp * wp; idx += NTD) {
@@ -1238,6 +1247,40 @@ int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
   return run_factor_kernels<CPLX>(S, H, Sv, nshift, L, work, st);
 }
 
+// Streams and events owned by the library for the subtree-parallel
+// factorization and SelInv (created on first use on the current device,
+// kept for the process).
+struct StreamPool {
+  int device = -1;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+};
+StreamPool g_pool;
+
+int ensure_pool(int nstreams, int nevents) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (g_pool.device != dev) {
+    g_pool.streams.clear();   // streams of another device are left alone
+    g_pool.events.clear();
+    g_pool.device = dev;
+  }
+  while ((int)g_pool.streams.size() < nstreams) {
+    hipStream_t s;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e != hipSuccess) return (int)e;
+    g_pool.streams.push_back(s);
+  }
+  while ((int)g_pool.events.size() < nevents) {
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return (int)e;
+    g_pool.events.push_back(ev);
+  }
+  return 0;
+}
+
 template <bool CPLX>
 int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int nshift, void* L,
                        void* work, hipStream_t st) {
@@ -1271,53 +1314,110 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
   const int TR = S.tile_rows;
   const double fm = CPLX ? 8.0 : 2.0;   // flops per multiply-add
   const double eb = CPLX ? 16.0 : 8.0;  // bytes per element
-  const size_t np = S.panels.size();
-  for (size_t ip = 0; ip < np; ++ip) {
-    const Panel& P = S.panels[ip];
+  // the panel work of one panel: left-looking update from the earlier
+  // columns of its supernode, LDL^T of the diagonal block, the rows below
+  auto panel_work = [&](const Panel& P, hipStream_t s) -> int {
     PanelK k = panel_args(S, P);
     if (k.p0 > 0) {
-      // left-looking: the panel's rows receive the earlier columns of its supernode
       const int nrows = k.ld - k.p0;
-      ProfScope ps(KC_UPDATE, st, fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0,
+      ProfScope ps(KC_UPDATE, s, fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0,
                    eb * nshift * ((double)nrows * k.p0 + 2.0 * nrows * k.wp));
       if (TR == 64)
-        hipLaunchKernelGGL((k_int_update<CPLX, 64>), dim3((nrows + 63) / 64, nshift), dim3(NT), 0, st, c, k);
+        hipLaunchKernelGGL((k_int_update<CPLX, 64>), dim3((nrows + 63) / 64, nshift), dim3(NT), 0, s, c, k);
       else
-        hipLaunchKernelGGL((k_int_update<CPLX, 128>), dim3((nrows + 127) / 128, nshift), dim3(NT), 0, st, c, k);
+        hipLaunchKernelGGL((k_int_update<CPLX, 128>), dim3((nrows + 127) / 128, nshift), dim3(NT), 0, s, c, k);
     }
     {
-      ProfScope ps(KC_DIAG, st, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0,
+      ProfScope ps(KC_DIAG, s, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0,
                    eb * nshift * (double)k.wp * (k.wp + 1));
-      hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NTD), 0, st, c, k);
+      hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NTD), 0, s, c, k);
     }
     if (k.nb > 0) {
       const int nt = (k.nb + TR - 1) / TR;
-      ProfScope ps(KC_TRSM, st, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0,
+      ProfScope ps(KC_TRSM, s, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0,
                    eb * nshift * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)));
       if (TR == 64)
-        hipLaunchKernelGGL((k_trsm<CPLX, 64>), dim3(nt, nshift), dim3(NT), 0, st, c, k);
+        hipLaunchKernelGGL((k_trsm<CPLX, 64>), dim3(nt, nshift), dim3(NT), 0, s, c, k);
       else
-        hipLaunchKernelGGL((k_trsm<CPLX, 128>), dim3(nt, nshift), dim3(NT), 0, st, c, k);
-    }
-    const bool last = (ip + 1 == np) || (S.panels[ip + 1].J != P.J);
-    const int32_t w = S.sfirst[P.J + 1] - S.sfirst[P.J];
-    const int32_t below = S.ld[P.J] - w;
-    if (last && below > 0) {
-      // right-looking: the whole supernode updates its ancestors once (K = w)
-      PanelK u = k;
-      u.p0 = 0;
-      u.wp = w;
-      u.nb = below;
-      const int ntj = (below + TM - 1) / TM, nti = (below + TR - 1) / TR;
-      ProfScope ps(KC_UPDATE, st, fm * nshift * (double)below * (below + 1) / 2.0 * w,
-                   eb * nshift * ((double)below * w + (double)below * (below + 1)));
-      if (TR == 64)
-        hipLaunchKernelGGL((k_update<CPLX, 64>), dim3(ntj * nti, nshift), dim3(NT), 0, st, c, u);
-      else
-        hipLaunchKernelGGL((k_update<CPLX, 128>), dim3(ntj * nti, nshift), dim3(NT), 0, st, c, u);
+        hipLaunchKernelGGL((k_trsm<CPLX, 128>), dim3(nt, nshift), dim3(NT), 0, s, c, k);
     }
     PXS_CHECK_LAUNCH();
+    return 0;
+  };
+  // right-looking: the whole supernode J updates its ancestors once (K = w),
+  // scattered into their panels; J's last panel describes its row list
+  auto scatter = [&](const Panel& P, hipStream_t s) -> int {
+    const int32_t w = S.sfirst[P.J + 1] - S.sfirst[P.J];
+    const int32_t below = S.ld[P.J] - w;
+    if (below <= 0) return 0;
+    PanelK u = panel_args(S, P);
+    u.p0 = 0;
+    u.wp = w;
+    u.nb = below;
+    const int ntj = (below + TM - 1) / TM, nti = (below + TR - 1) / TR;
+    ProfScope ps(KC_UPDATE, s, fm * nshift * (double)below * (below + 1) / 2.0 * w,
+                 eb * nshift * ((double)below * w + (double)below * (below + 1)));
+    if (TR == 64)
+      hipLaunchKernelGGL((k_update<CPLX, 64>), dim3(ntj * nti, nshift), dim3(NT), 0, s, c, u);
+    else
+      hipLaunchKernelGGL((k_update<CPLX, 128>), dim3(ntj * nti, nshift), dim3(NT), 0, s, c, u);
+    PXS_CHECK_LAUNCH();
+    return 0;
+  };
+  const size_t np = S.panels.size();
+  const int ns = S.nsuper;
+  const int NS = S.sel_nstreams;
+  if ((int)S.fac_order.size() != ns || (int)S.fac_child.size() != ns) return (int)hipErrorInvalidValue;
+  std::vector<int> pfirst(ns, -1), plast(ns, -1);
+  for (size_t ip = 0; ip < np; ++ip) {
+    const int J = S.panels[ip].J;
+    if (pfirst[J] < 0) pfirst[J] = (int)ip;
+    plast[J] = (int)ip;
   }
+  // Supernodes are issued in fac_order on every path, so each entry receives
+  // its scatters in the same order and the factors are bit-identical whether
+  // the subtree streams are used or not.  Inside a stream capture, or with
+  // one subtree stream, everything runs on the caller's stream.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  hipError_t he = hipStreamIsCapturing(st, &cap);
+  if (he != hipSuccess) return (int)he;
+  int err = 0;
+  if (cap != hipStreamCaptureStatusNone || NS <= 1) {
+    for (int J : S.fac_order) {
+      if (pfirst[J] < 0) continue;
+      for (int ip = pfirst[J]; ip <= plast[J]; ++ip)
+        if ((err = panel_work(S.panels[ip], st))) return err;
+      if ((err = scatter(S.panels[plast[J]], st))) return err;
+    }
+    return 0;
+  }
+  // subtree streams: the panel work of J on pool stream sel_stream[J] once
+  // the scatters into J are done (the scatter of fac_child[J] and, the
+  // caller's stream being in order, every scatter issued before it); the
+  // scatter of J on the caller's stream after J's panel work.  Scatters of
+  // different supernodes write the same ancestor entries, so they stay on
+  // the one stream, in fac_order.
+  if ((err = ensure_pool(NS, 2 * ns + 1))) return err;
+  hipEvent_t* evp = g_pool.events.data();   // evp[J]: panel work of J done
+  hipEvent_t* evs = evp + ns;               // evs[J]: scatter of J done
+  hipEvent_t evf = evp[2 * ns];             // assembly done
+  if ((he = hipEventRecord(evf, st)) != hipSuccess) return (int)he;
+  for (int J : S.fac_order) {
+    if (pfirst[J] < 0) continue;
+    hipStream_t sj = g_pool.streams[S.sel_stream[J]];
+    const int ch = S.fac_child[J];
+    if ((he = hipStreamWaitEvent(sj, ch >= 0 ? evs[ch] : evf, 0)) != hipSuccess) return (int)he;
+    for (int ip = pfirst[J]; ip <= plast[J]; ++ip)
+      if ((err = panel_work(S.panels[ip], sj))) return err;
+    if ((he = hipEventRecord(evp[J], sj)) != hipSuccess) return (int)he;
+    if (S.sparent[J] < 0) continue;   // a root: joined below
+    if ((he = hipStreamWaitEvent(st, evp[J], 0)) != hipSuccess) return (int)he;
+    if ((err = scatter(S.panels[plast[J]], st))) return err;
+    if ((he = hipEventRecord(evs[J], st)) != hipSuccess) return (int)he;
+  }
+  for (int J = 0; J < ns; ++J)
+    if (S.sparent[J] < 0 && pfirst[J] >= 0)
+      if ((he = hipStreamWaitEvent(st, evp[J], 0)) != hipSuccess) return (int)he;
   return 0;
 }
 
@@ -1325,39 +1425,6 @@ template int run_factor<true>(const Symbolic&, const double*, const double*, int
 template int run_factor<false>(const Symbolic&, const double*, const double*, int, const double*, void*, void*, hipStream_t);
 template int run_factor_kernels<true>(const Symbolic&, const double*, const double*, int, void*, void*, hipStream_t);
 template int run_factor_kernels<false>(const Symbolic&, const double*, const double*, int, void*, void*, hipStream_t);
-
-// Streams and events owned by the library for the subtree-parallel SelInv
-// (created on first use on the current device, kept for the process).
-struct StreamPool {
-  int device = -1;
-  std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> events;
-};
-StreamPool g_pool;
-
-int ensure_pool(int nstreams, int nevents) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return (int)e;
-  if (g_pool.device != dev) {
-    g_pool.streams.clear();   // streams of another device are left alone
-    g_pool.events.clear();
-    g_pool.device = dev;
-  }
-  while ((int)g_pool.streams.size() < nstreams) {
-    hipStream_t s;
-    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e != hipSuccess) return (int)e;
-    g_pool.streams.push_back(s);
-  }
-  while ((int)g_pool.events.size() < nevents) {
-    hipEvent_t ev;
-    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e != hipSuccess) return (int)e;
-    g_pool.events.push_back(ev);
-  }
-  return 0;
-}
 
 int64_t selinv_work_bytes(const Symbolic& S, int nshift) {
   const int chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;

@@ -79,6 +79,14 @@ struct Symbolic {
   std::vector<int64_t> gather_bytes;
   std::vector<uint8_t> cross_child;  // J has a child on another stream
   int32_t max_below_super = 0;      // max over supernodes of ld - w
+
+  // Factorization with the same subtree streams: supernodes are issued by
+  // height in the supernodal tree (leaves first, column order within a
+  // height), the panel work of J on stream sel_stream[J], every ancestor
+  // scatter on the caller's stream in that order.  fac_child[J] is the child
+  // of J issued last (-1 for a leaf): its scatter ends the scatters into J.
+  std::vector<int32_t> fac_order;
+  std::vector<int32_t> fac_child;
 };
 
 struct AnalyzeOptions {

@@ -591,6 +591,23 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
       g = std::max(g, (16 * c * c + 255) / 256 * 256);
     }
   }
+  {
+    // factorization issue order (children are numbered before parents)
+    std::vector<int32_t> height(ns, 0);
+    for (int32_t J = 0; J < ns; ++J)
+      if (S.sparent[J] >= 0) height[S.sparent[J]] = std::max(height[S.sparent[J]], height[J] + 1);
+    S.fac_order.resize(ns);
+    std::iota(S.fac_order.begin(), S.fac_order.end(), 0);
+    std::stable_sort(S.fac_order.begin(), S.fac_order.end(),
+                     [&](int32_t a, int32_t b) { return height[a] < height[b]; });
+    std::vector<int32_t> seq(ns);
+    for (int32_t i = 0; i < ns; ++i) seq[S.fac_order[i]] = i;
+    S.fac_child.assign(ns, -1);
+    for (int32_t J = 0; J < ns; ++J) {
+      const int32_t q = S.sparent[J];
+      if (q >= 0 && (S.fac_child[q] < 0 || seq[J] > seq[S.fac_child[q]])) S.fac_child[q] = J;
+    }
+  }
   S.selinv_chunk = std::max(0, opt.selinv_chunk);
   S.tile_rows = (opt.tile_rows == 128) ? 128 : 64;
   return 0;
