@@ -388,6 +388,39 @@ def test_graph_plan_replays_match_eager(torch_cuda):
         assert np.all(info == 0)
 
 
+def test_results_do_not_depend_on_the_subtree_streams(torch_cuda):
+    """Eager factorization and selected inversion on 1, 2, 4 or 8 subtree
+    streams (and the in-order path of a single stream) give the same
+    factors, selected inverses, pole sums, traces and inertia counts bit for
+    bit: the supernodes are issued in one order on every path and every
+    entry receives its scatters in that order."""
+    torch = torch_cuda
+    from paper_1405_0194_amd import binding as B
+    s = lattice.make_system("honeycomb", (9, 8), 13, 3.0, 77)
+    H = _dev(torch, s.hval)
+    S = _dev(torch, s.sval)
+    P = 24
+    sh, wt = B.poles(BETA, 1.0, 0.0, P, 2)
+    eps = np.array([-0.3, -0.01, 0.0, 0.2])
+    ref = None
+    for ns in (1, 2, 4, 8):
+        say("case: subtree streams", ns, "N", s.n)
+        a = B.Analysis.from_system(s, selinv_streams=ns)
+        f = B.Factorization(a, H, S, sh)
+        d = f.diag(5).cpu().numpy().copy()
+        f.selinv()
+        z = f.selected(3).cpu().numpy().copy()
+        out, tr = f.pole_sum(wt)
+        neg, info = B.inertia(a, H, S, eps)
+        got = (d, z, out.cpu().numpy().copy(), np.asarray(tr).copy(), np.asarray(neg).copy())
+        assert np.all(f.info == 0) and np.all(np.asarray(info) == 0)
+        if ref is None:
+            ref = got
+            continue
+        for x, y in zip(got, ref):
+            assert np.array_equal(np.asarray(x), np.asarray(y)), ns
+
+
 def test_maximum_batch_of_shifts(torch_cuda):
     """4096 shifts (the largest batch) in one factorization + SelInv;
     sampled shifts against the dense inverse."""
