@@ -17,6 +17,7 @@ inverse per shift) on a bounded sample, scaled to this workload.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -52,11 +53,16 @@ WORKLOADS = {
 }
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1405_0194_amd", "csrc", "numeric.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
+def kernel_source_hash(text=None):
+    """Hash of the kernel source's code: comments and layout do not count, so
+    a counter summary stays valid across edits of comments only."""
+    if text is None:
+        with open(os.path.join(ROOT, "paper_1405_0194_amd", "csrc", "numeric.hip")) as f:
+            text = f.read()
+    code = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    code = re.sub(r"//[^\n]*", " ", code)
+    code = " ".join(code.split())
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def measured_traffic(kernel, workload):

@@ -9,10 +9,12 @@
 // number of negative d_k is the inertia count.
 //
 // Execution model: every launch covers all shifts of a batch (grid.y) and all
-// tiles of one panel (a <= 64-column slice of a supernode).  Panels run in
-// factor order (left to right, supernodes in postorder) and SelInv order (the
-// reverse); within a launch, workgroups own disjoint outputs, so there are no
-// atomics on matrix data and results do not depend on scheduling.
+// tiles of one panel (a <= 64-column slice of a supernode).  The factorization
+// issues supernodes leaves first (by height in the supernodal tree, columns in
+// order within one), panels left to right; SelInv runs root to leaves.  Within
+// a launch, workgroups own disjoint outputs, so there are no atomics on matrix
+// data, and every entry receives its updates in one fixed order, so results
+// do not depend on scheduling or on the number of subtree streams.
 //
 // Per panel p of supernode J (row list E_J, own columns first), with
 // B = rows of E_J below the panel's diagonal block:
