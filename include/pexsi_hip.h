@@ -44,7 +44,7 @@
  *   - Threads: a bound symbolic handle is read-only and may serve calls on
  *     several streams.  Eager factorization and selected inversion with more
  *     than one subtree stream (pxs_factor, pxs_inertia, pxs_selinv,
- *     pxs_density_matrix; the real and complex-symmetric paths) run
+ *     pxs_density_matrix, pxs_factor_hermitian, pxs_inertia_hermitian) run
  *     independent subtrees on a process-wide pool of streams and events per
  *     device: issue such calls from one host thread at a time.  The results
  *     do not depend on the number of streams (bit-identical).  Graph plans
