@@ -115,6 +115,16 @@ typedef struct {
                                   8 * sum_k c_k (c_k + 1) / 2 */
   double flops_selinv;         /* 8 * sum_k (c_k^2 + c_k) */
   /* c_k = off-diagonal nonzeros of column k in the exact pattern of L */
+  double macs_exact[8];        /* the same multiply-adds per shift split by
+                                  the kernel class (pxs_profile_begin numbers)
+                                  that performs them: [1] factor updates,
+                                  [2] SelInv off-diagonal product, [3] panel
+                                  TRSM, [4] SelInv diagonal-block partials,
+                                  [6] diagonal-block LDL^T; [0] the SelInv
+                                  diagonal blocks finished in LDS; [5] (L-hat,
+                                  a by-product of the blocked algorithm) and
+                                  [7] are 0.  [1]+[3]+[6] = flops_factor / 8,
+                                  [0]+[2]+[4] = flops_selinv / 8. */
 } pxs_syminfo;
 
 /* ---------------------------------------------------------------------- */
@@ -296,15 +306,18 @@ void pxs_plan_free(pxs_plan plan);
  *         LDL^T, 7 assembly, 8 pole sum, 9 SelInv gather of Z_CC.
  * pxs_profile_end synchronises those events and returns the summed kernel
  * time (ms), the number of launches, their algorithmic flops (complex
- * multiply-add = 8 flops, on the stored supernodal structure, no tile
- * padding; for kernels 7, 8 and 9 their algorithmic HBM bytes instead) and, in
- * `bytes` (nullable), their algorithmic HBM bytes: every operand read once
- * and every result written once.
+ * multiply-add = 8 flops, real = 2, counted on the exact column structure
+ * of L as in pxs_syminfo.macs_exact; for kernels 7, 8 and 9 their
+ * algorithmic HBM bytes instead), in `bytes` (nullable) their algorithmic
+ * HBM bytes (every operand of the stored structure read once and every
+ * result written once) and in `stored` (nullable) their flops on the stored
+ * (relaxed supernodal) structure, explicit zeros included, no tile padding.
  * Process-wide state; not thread safe.  PXS_ESTATE if no profile is open;
  * PXS_EHIP (and no totals) if an event could not be created or recorded
  * during the profile. */
 pxs_status pxs_profile_begin(int32_t kernel);
-pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work, double* bytes);
+pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work, double* bytes,
+                           double* stored);
 
 /* Text of the last HIP or validation error seen by this thread (diagnostics). */
 const char* pxs_last_error(void);

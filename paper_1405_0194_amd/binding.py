@@ -42,7 +42,8 @@ class SymInfo(C.Structure):
                 ("work_fixed", C.c_int64), ("work_per_shift", C.c_int64),
                 ("gather_per_shift", C.c_int64), ("selinv_chunk", C.c_int64),
                 ("map_bytes", C.c_int64), ("max_front", C.c_int64),
-                ("flops_factor", C.c_double), ("flops_selinv", C.c_double)]
+                ("flops_factor", C.c_double), ("flops_selinv", C.c_double),
+                ("macs_exact", C.c_double * 8)]
 
 
 _P = C.c_void_p
@@ -85,7 +86,7 @@ def load():
         "pxs_plan_results": (C.c_int, [_P, _P, _P, _P]),
         "pxs_plan_free": (None, [_P]),
         "pxs_profile_begin": (C.c_int, [C.c_int32]),
-        "pxs_profile_end": (C.c_int, [_P, _P, _P, _P]),
+        "pxs_profile_end": (C.c_int, [_P, _P, _P, _P, _P]),
         "pxs_free_symbolic": (None, [_P]),
         "pxs_free_numeric": (None, [_P]),
         "pxs_status_string": (C.c_char_p, [C.c_int]),
@@ -187,6 +188,7 @@ class Analysis:
         info = SymInfo()
         _check("pxs_symbolic_info", lib.pxs_symbolic_info(h, C.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in SymInfo._fields_}
+        self.info["macs_exact"] = list(info.macs_exact)
         self.maps = None
 
     @classmethod
@@ -550,14 +552,20 @@ def profile_begin(kernel: str):
     _check("pxs_profile_begin", load().pxs_profile_begin(KERNELS[kernel]))
 
 
-def profile_end(with_bytes=False):
-    """Returns (total kernel ms, launches, algorithmic flops or bytes), plus
-    the algorithmic HBM bytes when with_bytes is set."""
+def profile_end(with_bytes=False, with_stored=False):
+    """Returns (total kernel ms, launches, algorithmic flops on the exact
+    structure of L or bytes), plus the algorithmic HBM bytes when with_bytes
+    is set and the flops on the stored structure when with_stored is set."""
     ms = C.c_double()
     n = C.c_int64()
     w = C.c_double()
     b = C.c_double()
-    _check("pxs_profile_end", load().pxs_profile_end(C.byref(ms), C.byref(n), C.byref(w), C.byref(b)))
+    st = C.c_double()
+    _check("pxs_profile_end", load().pxs_profile_end(C.byref(ms), C.byref(n), C.byref(w), C.byref(b),
+                                                     C.byref(st)))
+    out = (ms.value, n.value, w.value)
     if with_bytes:
-        return ms.value, n.value, w.value, b.value
-    return ms.value, n.value, w.value
+        out += (b.value,)
+    if with_stored:
+        out += (st.value,)
+    return out

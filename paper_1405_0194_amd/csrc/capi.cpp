@@ -166,6 +166,15 @@ pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info) {
   info->max_front = S.max_front;
   info->flops_factor = S.flops_factor;
   info->flops_selinv = S.flops_selinv;
+  for (const pxs::PanelMacs& m : S.xm_panel) {
+    info->macs_exact[pxs::KC_UPDATE] += m.intu;
+    info->macs_exact[pxs::KC_DIAG] += m.diag;
+    info->macs_exact[pxs::KC_TRSM] += m.trsm;
+    info->macs_exact[pxs::KC_SELINV_OFF] += m.off;
+    info->macs_exact[pxs::KC_SELINV_DIAG] += m.sdiag;
+    info->macs_exact[0] += m.sfinal;
+  }
+  for (double u : S.xm_update) info->macs_exact[pxs::KC_UPDATE] += u;
   return PXS_OK;
 }
 
@@ -549,15 +558,17 @@ pxs_status pxs_profile_begin(int32_t kernel) {
   return PXS_OK;
 }
 
-pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work, double* bytes) {
+pxs_status pxs_profile_end(double* total_ms, int64_t* launches, double* work, double* bytes,
+                           double* stored) {
   if (!total_ms || !launches || !work) return PXS_EINVAL;
-  double b = 0.0;
-  int e = pxs::profile_end(total_ms, launches, work, &b);
+  double b = 0.0, sw = 0.0;
+  int e = pxs::profile_end(total_ms, launches, work, &b, &sw);
   if (e == -1) {
     g_last_error = "pxs_profile_end: no profile is open";
     return PXS_ESTATE;
   }
   if (bytes) *bytes = b;
+  if (stored) *stored = sw;
   if (e != 0) return hip_fail(e);
   return PXS_OK;
 }

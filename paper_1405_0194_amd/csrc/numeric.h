@@ -26,7 +26,7 @@ constexpr int64_t WK_FIXED_BYTES = 1 << 20;
 enum KernelClass { KC_NONE = 0, KC_UPDATE = 1, KC_SELINV_OFF = 2, KC_TRSM = 3, KC_SELINV_DIAG = 4,
                    KC_LHAT = 5, KC_DIAG = 6, KC_ASSEMBLE = 7, KC_POLESUM = 8, KC_GATHER = 9 };
 int profile_begin(int kernel);
-int profile_end(double* ms, int64_t* launches, double* work, double* bytes);
+int profile_end(double* ms, int64_t* launches, double* work, double* bytes, double* stored);
 
 template <bool CPLX>
 int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,

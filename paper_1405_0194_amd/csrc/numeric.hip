@@ -1097,8 +1097,9 @@ struct Profiler {
   std::vector<hipEvent_t> ev;   // pool, reused across profiles
   size_t used = 0;
   int64_t launches = 0;
-  double work = 0.0;    // algorithmic flops (bytes for the memory-bound classes)
+  double work = 0.0;    // algorithmic flops on the exact structure of L (bytes for the memory-bound classes)
   double bytes = 0.0;   // algorithmic HBM bytes: operands read once, results written once
+  double stored = 0.0;  // flops on the stored (relaxed supernodal) structure
   int failed = 0;       // HIP error of an event create/record inside the profile, 0 if none
 };
 Profiler g_prof;
@@ -1106,9 +1107,11 @@ Profiler g_prof;
 struct ProfScope {
   hipStream_t st;
   bool on;
-  double w_, b_;
-  ProfScope(int kernel, hipStream_t s, double work, double bytes)
-      : st(s), on(g_prof.kernel == kernel && kernel != KC_NONE), w_(work), b_(bytes) {
+  double w_, b_, s_;
+  // work: exact algorithmic flops (bytes for the memory-bound classes);
+  // stored: flops on the stored structure
+  ProfScope(int kernel, hipStream_t s, double work, double bytes, double stored)
+      : st(s), on(g_prof.kernel == kernel && kernel != KC_NONE), w_(work), b_(bytes), s_(stored) {
     if (!on) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
@@ -1136,6 +1139,7 @@ struct ProfScope {
     g_prof.launches += 1;
     g_prof.work += w_;
     g_prof.bytes += b_;
+    g_prof.stored += s_;
   }
 };
 
@@ -1199,11 +1203,12 @@ int profile_begin(int kernel) {
   g_prof.launches = 0;
   g_prof.work = 0.0;
   g_prof.bytes = 0.0;
+  g_prof.stored = 0.0;
   g_prof.failed = 0;
   return 0;
 }
 
-int profile_end(double* ms, int64_t* launches, double* work, double* bytes) {
+int profile_end(double* ms, int64_t* launches, double* work, double* bytes, double* stored) {
   if (g_prof.kernel == KC_NONE) return -1;   // no profile open
   if (g_prof.failed) {                        // totals would be partial
     const int f = g_prof.failed;
@@ -1224,6 +1229,7 @@ int profile_end(double* ms, int64_t* launches, double* work, double* bytes) {
   *launches = g_prof.launches;
   *work = g_prof.work;
   *bytes = g_prof.bytes;
+  *stored = g_prof.stored;
   g_prof.kernel = KC_NONE;
   g_prof.used = 0;
   return 0;
@@ -1307,7 +1313,7 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
   {
     // bytes: H, S, offsets read once per shift block; one element written per entry and shift
     const double ab = (double)S.nnz_lower * (24.0 + (CPLX ? 16.0 : 8.0) * nshift);
-    ProfScope ps(KC_ASSEMBLE, st, ab, ab);
+    ProfScope ps(KC_ASSEMBLE, st, ab, ab, ab);
     hipLaunchKernelGGL(k_assemble<CPLX>, dim3(blocks_for(S.nnz_lower, 2048), nshift), dim3(NT), 0, st,
                        (double*)L, S.nnzL_store, H, Sv, eoff, S.nnz_lower, (const double*)(w + WK_SHIFTS));
   }
@@ -1320,24 +1326,25 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
   // columns of its supernode, LDL^T of the diagonal block, the rows below
   auto panel_work = [&](const Panel& P, hipStream_t s) -> int {
     PanelK k = panel_args(S, P);
+    const PanelMacs& xm = S.xm_panel[&P - S.panels.data()];
     if (k.p0 > 0) {
       const int nrows = k.ld - k.p0;
-      ProfScope ps(KC_UPDATE, s, fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0,
-                   eb * nshift * ((double)nrows * k.p0 + 2.0 * nrows * k.wp));
+      ProfScope ps(KC_UPDATE, s, fm * nshift * xm.intu, eb * nshift * ((double)nrows * k.p0 + 2.0 * nrows * k.wp),
+                   fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0);
       if (TR == 64)
         hipLaunchKernelGGL((k_int_update<CPLX, 64>), dim3((nrows + 63) / 64, nshift), dim3(NT), 0, s, c, k);
       else
         hipLaunchKernelGGL((k_int_update<CPLX, 128>), dim3((nrows + 127) / 128, nshift), dim3(NT), 0, s, c, k);
     }
     {
-      ProfScope ps(KC_DIAG, s, fm * nshift * (double)k.wp * k.wp * k.wp / 3.0,
-                   eb * nshift * (double)k.wp * (k.wp + 1));
+      ProfScope ps(KC_DIAG, s, fm * nshift * xm.diag, eb * nshift * (double)k.wp * (k.wp + 1),
+                   fm * nshift * (double)k.wp * k.wp * k.wp / 3.0);
       hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NTD), 0, s, c, k);
     }
     if (k.nb > 0) {
       const int nt = (k.nb + TR - 1) / TR;
-      ProfScope ps(KC_TRSM, s, fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0,
-                   eb * nshift * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)));
+      ProfScope ps(KC_TRSM, s, fm * nshift * xm.trsm, eb * nshift * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)),
+                   fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
       if (TR == 64)
         hipLaunchKernelGGL((k_trsm<CPLX, 64>), dim3(nt, nshift), dim3(NT), 0, s, c, k);
       else
@@ -1357,8 +1364,9 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
     u.wp = w;
     u.nb = below;
     const int ntj = (below + TM - 1) / TM, nti = (below + TR - 1) / TR;
-    ProfScope ps(KC_UPDATE, s, fm * nshift * (double)below * (below + 1) / 2.0 * w,
-                 eb * nshift * ((double)below * w + (double)below * (below + 1)));
+    ProfScope ps(KC_UPDATE, s, fm * nshift * S.xm_update[P.J],
+                 eb * nshift * ((double)below * w + (double)below * (below + 1)),
+                 fm * nshift * (double)below * (below + 1) / 2.0 * w);
     if (TR == 64)
       hipLaunchKernelGGL((k_update<CPLX, 64>), dim3(ntj * nti, nshift), dim3(NT), 0, s, c, u);
     else
@@ -1510,17 +1518,19 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
         const int nt = (g.c + TM - 1) / TM;
         // bytes: the lower triangle of Z_CC read from the ancestors and written to G, relative positions
         const double gb = (32.0 * nsh + 4.0) * 0.5 * g.c * (g.c + 1);
-        ProfScope ps(KC_GATHER, sj, gb, gb);
+        ProfScope ps(KC_GATHER, sj, gb, gb, gb);
         hipLaunchKernelGGL(k_gather_cc, dim3(nt * (nt + 1) / 2, nsh), dim3(NT), 0, sj, c, g);
       }
       for (int ip = last; ip >= first; --ip) {
         PanelK k = panel_args(S, S.panels[ip]);
         k.sh0 = sh0;
+        const PanelMacs& xm = S.xm_panel[ip];
         if (k.nb > 0) {
           const int nt = (k.nb + TR - 1) / TR;
           {
-            ProfScope ps(KC_LHAT, sj, 8.0 * nsh * (double)k.nb * k.wp * (k.wp + 1) / 2.0,
-                         16.0 * nsh * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)));
+            // L-hat is a by-product of the blocked algorithm: no exact flops
+            ProfScope ps(KC_LHAT, sj, 0.0, 16.0 * nsh * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)),
+                         8.0 * nsh * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
             if (TR == 64)
               hipLaunchKernelGGL(k_lhat<64>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
             else
@@ -1528,16 +1538,18 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
           }
           {
             // bytes: Z_BB (one triangle), L-hat read, Z_Bp written
-            ProfScope ps(KC_SELINV_OFF, sj, 8.0 * nsh * (double)k.nb * k.nb * k.wp,
-                         16.0 * nsh * (0.5 * k.nb * (k.nb + 1) + 2.0 * k.nb * k.wp));
+            ProfScope ps(KC_SELINV_OFF, sj, 8.0 * nsh * xm.off,
+                         16.0 * nsh * (0.5 * k.nb * (k.nb + 1) + 2.0 * k.nb * k.wp),
+                         8.0 * nsh * (double)k.nb * k.nb * k.wp);
             if (TR == 64)
               hipLaunchKernelGGL(k_selinv_off<64>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
             else
               hipLaunchKernelGGL(k_selinv_off<128>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
           }
           {
-            ProfScope ps(KC_SELINV_DIAG, sj, 8.0 * nsh * (double)k.nb * k.wp * k.wp,
-                         16.0 * nsh * (2.0 * k.nb * k.wp + (double)k.wp * k.wp));
+            ProfScope ps(KC_SELINV_DIAG, sj, 8.0 * nsh * xm.sdiag,
+                         16.0 * nsh * (2.0 * k.nb * k.wp + (double)k.wp * k.wp),
+                         8.0 * nsh * (double)k.nb * k.wp * k.wp);
             hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, nsh), dim3(NT), 0, sj, c, k);
           }
         }
@@ -1571,7 +1583,7 @@ int run_pole_sum_kernels(const Symbolic& S, int nshift, const void* L, void* wor
   const int nb = blocks_for(S.nnz_lower, POLESUM_BLOCKS);
   // bytes: one complex per entry and shift, offsets, flags, H, S, nsets outputs
   const double ab = (double)S.nnz_lower * (16.0 * nshift + 28.0 + 8.0 * nsets);
-  ProfScope ps(KC_POLESUM, st, ab, ab);
+  ProfScope ps(KC_POLESUM, st, ab, ab, ab);
   hipLaunchKernelGGL(k_pole_sum, dim3(nb), dim3(NT), 0, st, (const double*)L, S.nnzL_store, nshift,
                      (const double*)(w + WK_WEIGHTS), nsets, (const int64_t*)(m + S.o_entry_off),
                      (const int32_t*)(m + S.o_entry_diag), S.nnz_lower, H, Sv, out,

@@ -18,6 +18,20 @@ struct Panel {
   int32_t nb_rows;  // rows below the panel's diagonal block (= ld_J - p0 - wp)
 };
 
+// Multiply-adds per shift on the exact column structure of L that each
+// kernel of one panel performs (symbolic.cpp: they partition
+// sum_k c_k (c_k + 1) / 2 for the factorization and sum_k (c_k^2 + c_k) for
+// selected inversion).  The stored (relaxed supernodal) structure can hold
+// explicit zeros, which the kernels multiply but which are not counted here.
+struct PanelMacs {
+  double intu = 0.0;   // left-looking update from the earlier panels of the supernode
+  double diag = 0.0;   // LDL^T of the diagonal block
+  double trsm = 0.0;   // rows below the diagonal block
+  double off = 0.0;    // SelInv: Z_BB times L-hat
+  double sdiag = 0.0;  // SelInv: diagonal-block partials
+  double sfinal = 0.0; // SelInv: diagonal block in LDS (incl. the diagonal terms)
+};
+
 // Result of the symbolic analysis (symbolic.cpp).  All indices are 0-based;
 // "new" indices are positions after the fill-reducing permutation.
 struct Symbolic {
@@ -54,6 +68,8 @@ struct Symbolic {
   std::vector<int32_t> entry_diag;   // 1 on the diagonal; 2 if the storage holds the entry's transpose; else 0
 
   std::vector<Panel> panels;        // factor order; selected inversion runs backwards
+  std::vector<PanelMacs> xm_panel;  // exact multiply-adds per shift, one per panel
+  std::vector<double> xm_update;    // exact multiply-adds per shift of each supernode's ancestor update
   int64_t max_below = 0;            // max nb_rows over panels
   int32_t max_split = 1;            // split-K pieces of the diagonal SelInv update
 

@@ -380,13 +380,37 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
     }
   }
 
+  // Panels cut every supernode into column blocks of panel_width (the
+  // numeric kernels' unit); pbase[J] is the index of J's first panel.
+  const int32_t pwid = std::max(1, std::min(64, opt.panel_width));
+  std::vector<int64_t> pbase(ns + 1, 0);
+  for (int32_t J = 0; J < ns; ++J) {
+    const int32_t w = nbptr[sbfirst[J + 1]] - nbptr[sbfirst[J]];
+    pbase[J + 1] = pbase[J] + (w + pwid - 1) / pwid;
+  }
+  S.xm_panel.assign((size_t)pbase[ns], PanelMacs{});
+  S.xm_update.assign(ns, 0.0);
+
   // exact block-level pattern of L (block elimination tree) for the flop
   // model and nnz(L): struct(t) = upper neighbours of t plus the structures
-  // of its block-etree children, minus t itself.
+  // of its block-etree children, minus t itself.  The structure of column k
+  // of block t is then the later columns of t plus every column of the
+  // blocks in struct(t).
+  //
+  // Along the way the exact multiply-adds of every column are split by the
+  // kernel that performs them (per shift; c = a + g + e off-diagonal
+  // nonzeros of column k: a inside k's panel, g in the later panels of its
+  // supernode, e below the supernode, b = g + e):
+  //   factor  c(c+1)/2 = a(a+1)/2 [diagonal block] + a b [panel TRSM]
+  //           + g(g+1)/2 + g e [internal updates of the later panels]
+  //           + e(e+1)/2 [the supernode's update of its ancestors],
+  //   SelInv  c^2 + c = b^2 [Z_BB times L-hat] + 2 a b [diagonal-block
+  //           partials] + a^2 + a + b [diagonal block in LDS].
   {
     std::vector<std::vector<int32_t>> st(nblk);
     std::vector<std::vector<int32_t>> ch(nblk);
     std::vector<int32_t> mark(nblk, -1);
+    std::vector<int64_t> rs, re, rc;   // ranges of struct(t) and their cumulative sizes
     double ff = 0.0, fs = 0.0;
     int64_t nnzx = 0;
     for (int32_t t = 0; t < nblk; ++t) {
@@ -400,13 +424,55 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
       }
       std::sort(s.begin(), s.end());
       int64_t below = 0;
-      for (int32_t u : s) below += nbptr[u + 1] - nbptr[u];
+      rs.clear();
+      re.clear();
+      rc.clear();
+      for (int32_t u : s) {
+        rs.push_back(nbptr[u]);
+        re.push_back(nbptr[u + 1]);
+        rc.push_back(below);
+        below += nbptr[u + 1] - nbptr[u];
+      }
       const int32_t o = nbptr[t + 1] - nbptr[t];
       for (int32_t c = 0; c < o; ++c) {
         double ck = (double)(o - 1 - c) + (double)below;
         ff += 8.0 * ck * (ck + 1.0) / 2.0;
         fs += 8.0 * (ck * ck + ck);
         nnzx += (int64_t)ck + 1;
+      }
+      // rows of struct(t)'s blocks below x
+      auto fbelow = [&](int64_t x) -> int64_t {
+        const size_t i = (size_t)(std::lower_bound(rs.begin(), rs.end(), x) - rs.begin());
+        if (i == 0) return 0;
+        return rc[i - 1] + std::min(x, re[i - 1]) - rs[i - 1];
+      };
+      const int32_t J = snode_of_blk[t];
+      const int64_t sj0 = nbptr[sbfirst[J]], sj1 = nbptr[sbfirst[J + 1]];
+      const int64_t bend = nbptr[t + 1];
+      for (int64_t k = nbptr[t]; k < bend; ++k) {
+        // structure rows of column k in [lo, hi)
+        auto cnt = [&](int64_t lo, int64_t hi) -> double {
+          if (hi <= lo) return 0.0;
+          const int64_t inb = std::max<int64_t>(0, std::min(hi, bend) - std::max(lo, k + 1));
+          return (double)(inb + fbelow(hi) - fbelow(lo));
+        };
+        const int64_t q = (k - sj0) / pwid;
+        const int64_t fe = std::min(sj0 + (q + 1) * pwid, sj1);
+        const double ck = (double)(bend - 1 - k) + (double)below;
+        const double a = cnt(k + 1, fe), g = cnt(fe, sj1), e = ck - a - g, b = g + e;
+        PanelMacs& pm = S.xm_panel[(size_t)(pbase[J] + q)];
+        pm.diag += 0.5 * a * (a + 1.0);
+        pm.trsm += a * b;
+        pm.off += b * b;
+        pm.sdiag += 2.0 * a * b;
+        pm.sfinal += a * a + a + b;
+        S.xm_update[J] += 0.5 * e * (e + 1.0);
+        const int64_t nq = pbase[J + 1] - pbase[J];
+        for (int64_t q2 = q + 1; q2 < nq; ++q2) {
+          const int64_t f2 = sj0 + q2 * pwid, fe2 = std::min(f2 + pwid, sj1);
+          const double s2 = cnt(f2, fe2);
+          if (s2 > 0.0) S.xm_panel[(size_t)(pbase[J] + q2)].intu += 0.5 * s2 * (s2 + 1.0) + s2 * cnt(fe2, INT64_MAX / 4);
+        }
       }
       if (!s.empty()) ch[s[0]].push_back(t);
     }
@@ -527,6 +593,7 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
       S.panels.push_back(P);
     }
   }
+  if (S.panels.size() != S.xm_panel.size()) { msg = "internal: panel count"; return -1; }
   // workspace (bytes): per shift the SelInv panel product L_hat
   // (max_below x panel_width complex), the split-K partials of the diagonal
   // block update (max_split x 64 x 64 complex) and the shift, weight and

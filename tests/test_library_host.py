@@ -214,3 +214,63 @@ def test_empty_and_oversized_inputs_rejected():
         code = lib.pxs_density_matrix(a._h, None, None, 1000.0, 1.0, 0.0, P, nsets, None, None, None,
                                       None, None, None, None, None)
         assert code == B.PXS_EINVAL, (P, nsets)
+
+
+def _exact_macs_by_class(a, Lx, pw):
+    """Brute force: the multiply-adds of every column on the exact pattern
+    (boolean elimination) split by the kernel that performs them, for
+    panels of pw columns inside the exported supernodes."""
+    ex = a.export()
+    sp = ex["super_ptr"]
+    n = Lx.shape[0]
+    got = np.zeros(8)
+    owner = np.zeros(n, dtype=np.int64)
+    for J in range(sp.shape[0] - 1):
+        owner[sp[J]:sp[J + 1]] = J
+    for k in range(n):
+        rows = np.nonzero(Lx[k + 1:, k])[0] + k + 1
+        J = owner[k]
+        s0, s1 = sp[J], sp[J + 1]
+        fe = min(s0 + ((k - s0) // pw + 1) * pw, s1)
+        a_ = np.sum(rows < fe)
+        g = np.sum((rows >= fe) & (rows < s1))
+        e = np.sum(rows >= s1)
+        b = g + e
+        got[6] += a_ * (a_ + 1) / 2      # diagonal block
+        got[3] += a_ * b                 # TRSM
+        got[1] += g * (g + 1) / 2 + g * e + e * (e + 1) / 2   # updates
+        got[2] += b * b                  # SelInv Z_BB L-hat
+        got[4] += 2 * a_ * b             # SelInv diagonal partials
+        got[0] += a_ * a_ + a_ + b       # SelInv diagonal block in LDS
+    return got
+
+
+@pytest.mark.parametrize("seed,pw", [(1, 5), (2, 3), (4, 64)])
+def test_exact_macs_per_kernel_class_random(seed, pw):
+    """The per-kernel-class exact counts (the roofline numerators) equal a
+    brute-force count on the boolean elimination pattern and partition the
+    factor and SelInv flop formulas."""
+    rng = np.random.default_rng(seed)
+    n = 70
+    P = rng.uniform(size=(n, n)) < 0.05
+    P = P | P.T | np.eye(n, dtype=bool)
+    colptr, rows = _lower_csc_from_dense(P)
+    a = B.Analysis(n, colptr, rows, leaf_cols=12, panel_width=pw)
+    ex = a.export()
+    Lx = osym.fill_pattern(osym.permute(P, ex["perm"]))
+    want = _exact_macs_by_class(a, Lx, pw)
+    got = np.array(a.info["macs_exact"])
+    assert np.allclose(got, want, rtol=1e-12, atol=0), (got, want)
+    assert got[5] == 0.0 and got[7] == 0.0
+    i = a.info
+    assert 8.0 * (got[1] + got[3] + got[6]) == pytest.approx(i["flops_factor"], rel=1e-12)
+    assert 8.0 * (got[0] + got[2] + got[4]) == pytest.approx(i["flops_selinv"], rel=1e-12)
+
+
+def test_exact_macs_per_kernel_class_atom_blocks():
+    s = lattice.make_system("honeycomb", (4, 3), 3, 3.0, 5, periodic=False)
+    a = B.Analysis.from_system(s, leaf_cols=9, panel_width=4)
+    Pd = osym.dense_pattern_from_lower_csc(s.n, s.colptr, s.rowind)
+    Lx = osym.fill_pattern(osym.permute(Pd, a.export()["perm"]))
+    want = _exact_macs_by_class(a, Lx, 4)
+    assert np.allclose(np.array(a.info["macs_exact"]), want, rtol=1e-12, atol=0)
