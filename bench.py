@@ -455,18 +455,12 @@ def main():
         a = tune.tuned_analysis(s, lattice.CONFIG_POLES[cfg])
     # SelInv works on shift chunks when the whole batch's workspace would not
     # fit beside the factors (the cubic bulk: 201 GB of factors for 80 shifts)
-    budget = int(args.hbm_budget_gib * 2**30)
-    need = a.info["bytes_per_shift"] * P + a.workspace_size(P)
-    if need > budget and not args.selinv_chunk:
-        for ch in (40, 20, 16, 10, 8, 5, 4, 2, 1):
-            if ch >= P:
-                continue
-            a2 = B.Analysis.from_system(s, **{**a.options, "selinv_chunk": ch})
-            if a2.info["bytes_per_shift"] * P + a2.workspace_size(P) <= budget:
-                a = a2
-                break
-        print(f"# SelInv chunk {a.options['selinv_chunk']} shifts to fit {args.hbm_budget_gib} GiB",
-              file=sys.stderr, flush=True)
+    if not args.selinv_chunk:
+        from paper_1405_0194_amd import tune
+        a = tune.fit_to_budget(s, a, P, int(args.hbm_budget_gib * 2**30))
+        if a.options["selinv_chunk"]:
+            print(f"# SelInv chunk {a.options['selinv_chunk']} shifts to fit {args.hbm_budget_gib} GiB",
+                  file=sys.stderr, flush=True)
     t_an = time.perf_counter() - t_an
     t_bind = time.perf_counter()
     a.bind()

@@ -106,18 +106,26 @@ def spectrum_bound(colptr, rowind, hval, sval):
     cols = np.repeat(np.arange(n), np.diff(colptr))
     rows = rowind.astype(np.int64)
     off = rows != cols
-    hrow = np.zeros(n)
-    np.add.at(hrow, rows, np.abs(hval))
-    np.add.at(hrow, cols[off], np.abs(hval[off]))
-    srow = np.zeros(n)
-    np.add.at(srow, rows[off], np.abs(sval[off]))
-    np.add.at(srow, cols[off], np.abs(sval[off]))
+    ah, as_ = np.abs(hval), np.abs(sval)
+    hrow = np.bincount(rows, ah, minlength=n) + np.bincount(cols[off], ah[off], minlength=n)
+    srow = np.bincount(rows[off], as_[off], minlength=n) + np.bincount(cols[off], as_[off], minlength=n)
     sdiag = np.zeros(n)
     sdiag[rows[~off]] = np.real(sval[~off])
     lo = float(np.min(sdiag - srow))
     if lo <= 0.0:
         return None
     return float(np.max(hrow)) / lo
+
+
+def pencil_dE(colptr, rowind, hval, sval, mu):
+    """Delta E of the pole table for a pencil given on its lower triangle:
+    the Gershgorin bound on max |eps| plus |mu|, which bounds max |eps - mu|
+    over the spectrum.  Raises ValueError when S is not strictly diagonally
+    dominant (then the caller must give Delta E)."""
+    bound = spectrum_bound(colptr, rowind, hval, sval)
+    if bound is None:
+        raise ValueError("S is not strictly diagonally dominant: pass dE, a bound on max |eps - mu|")
+    return bound + abs(mu)
 
 
 def _on(stream):
@@ -224,10 +232,7 @@ class Solver:
         n, colptr, rowind, hval, sval = lower_csc(H, S)
         herm = np.iscomplexobj(hval)
         if dE is None:
-            bound = spectrum_bound(colptr, rowind, hval, sval)
-            if bound is None:
-                raise ValueError("S is not strictly diagonally dominant: pass dE, a bound on max |eps - mu|")
-            dE = bound + abs(mu)
+            dE = pencil_dE(colptr, rowind, hval, sval, mu)
         e = self._entry(n, colptr, rowind, blocks, coords)
         a = e["analysis"]
         Hd = torch.from_numpy(hval).to(self.device)

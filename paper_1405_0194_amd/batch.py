@@ -15,11 +15,19 @@ from __future__ import annotations
 
 import dataclasses
 import time
+from typing import Optional
 
 import numpy as np
 
 from . import binding as B
+from .api import pencil_dE
 from .lattice import BETA_300K
+
+
+def job_dE(system, mu):
+    """Delta E of a job's pole table: the Gershgorin bound of its pencil
+    plus |mu| (raises when S is not diagonally dominant)."""
+    return pencil_dE(system.colptr, system.rowind, system.hval, system.sval, mu)
 
 
 @dataclasses.dataclass
@@ -29,6 +37,7 @@ class Job:
     mu: float = 0.0
     beta: float = BETA_300K
     nsets: int = 2
+    dE: Optional[float] = None  # bound on max |eps - mu|; None: Gershgorin bound + |mu|
     analysis: object = None
     footprint: int = 0          # device bytes while running (factor + workspace + output)
     flops: float = 0.0
@@ -75,6 +84,8 @@ class BatchRunner:
         self.keep = keep_outputs
         self.streams = [torch.cuda.Stream(device=device) for _ in range(max(1, nstreams))]
         for j in self.jobs:
+            if j.dE is None:
+                j.dE = job_dE(j.system, j.mu)
             if j.analysis is None:
                 if tuned is not None:
                     from .tune import tuned_analysis
@@ -120,7 +131,7 @@ class BatchRunner:
                     H, S = self._values(j)
                     L, W = _buffers(j, self.device)
                     plan = B.Plan(j.analysis, H, S, j.poles, nsets=j.nsets, L=L, work=W, device=self.device)
-                    sh, wt = B.poles(j.beta, 1.0 + abs(j.mu), j.mu, j.poles, j.nsets)
+                    sh, wt = B.poles(j.beta, j.dE, j.mu, j.poles, j.nsets)
                     j.t_submit = time.perf_counter()
                     plan.run(sh, wt, stream=st, sync=False)
                     ev = torch.cuda.Event()

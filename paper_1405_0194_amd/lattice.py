@@ -351,9 +351,11 @@ def _dims_for(kind, n_target):
 
 
 def batch_systems(count: int = 64, seed: int = CONFIG_SEED_BASE + 3,
-                  n_lo: float = 500.0, n_hi: float = 8000.0):
+                  n_lo: float = 500.0, n_hi: float = 8000.0, only=None):
     """The uneven batch: kind = s mod 3 (chain / honeycomb / cubic), target
-    size log-uniform in [n_lo, n_hi], pole count uniform in [40, 80] (even)."""
+    size log-uniform in [n_lo, n_hi], pole count uniform in [40, 80] (even).
+    only: indices of the systems to build (the others are drawn but not
+    built, so a subset equals the same systems of the whole batch)."""
     rng = np.random.default_rng(seed)
     out = []
     kinds = ("chain", "honeycomb", "cubic")
@@ -361,6 +363,8 @@ def batch_systems(count: int = 64, seed: int = CONFIG_SEED_BASE + 3,
         kind = kinds[s % 3]
         n_t = math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))
         P = 2 * int(rng.integers(20, 41))
+        if only is not None and s not in only:
+            continue
         dims, orb, cut = _dims_for(kind, n_t)
         out.append((make_system(kind, dims, orb, cut, seed * 1000 + s), P))
     return out

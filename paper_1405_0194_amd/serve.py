@@ -30,6 +30,7 @@ from typing import Optional
 import numpy as np
 
 from . import binding as B
+from .batch import job_dE
 from .lattice import BETA_300K
 
 
@@ -51,6 +52,7 @@ class Request:
     eps: Optional[np.ndarray] = None
     arrival: float = 0.0
     nsets: int = 2
+    dE: Optional[float] = None   # bound on max |eps - mu|; None: Gershgorin bound + |mu|
     rid: int = -1
     # filled by the server
     traces: object = None
@@ -208,19 +210,24 @@ class Server:
                                        stream=st)
                     counts.append(neg)
                 req.neg_counts = np.concatenate(counts)
-            sh, wt = B.poles(req.beta, 1.0 + abs(req.mu), req.mu, req.poles, req.nsets)
+            if req.dE is None:
+                req.dE = job_dE(req.system, req.mu)
+            sh, wt = B.poles(req.beta, req.dE, req.mu, req.poles, req.nsets)
             req.chunks = (req.poles + r.chunk - 1) // r.chunk
             if req.chunks == 1:
                 r.plan(req.poles, False).run(sh, wt, stream=st, sync=False)
             else:
                 self.stats["chunked"] += 1
                 tr = np.zeros((req.nsets, 2))
+                infos = []
                 for c0 in range(0, req.poles, r.chunk):
                     c1 = min(req.poles, c0 + r.chunk)
                     p = r.plan(c1 - c0, c0 > 0)
-                    _, t, _ = p.run(sh[c0:c1], wt[:, c0:c1], stream=st, sync=True)
+                    _, t, inf = p.run(sh[c0:c1], wt[:, c0:c1], stream=st, sync=True)
                     tr += t
+                    infos.append(inf)
                 req.traces = tr
+                req.info = np.concatenate(infos)
             ev = torch.cuda.Event()
             ev.record(st)
         return ev

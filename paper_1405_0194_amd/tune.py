@@ -56,6 +56,26 @@ def tuned_analysis(system, P, cache=None, path=DEFAULT_CACHE):
     return B.Analysis.from_system(system, **opts)
 
 
+def fit_to_budget(system, analysis, P, budget_bytes):
+    """An analysis whose factor storage and workspace for P complex shifts
+    fit budget_bytes of device memory: `analysis` itself when it fits,
+    else the same options with the largest SelInv shift chunk (40, 20, 16,
+    10, 8, 5, 4, 2 or 1 shifts per pass; the dense Z_CC workspace grows
+    with the chunk) that fits.  Raises if none does."""
+    def need(a):
+        return a.info["bytes_per_shift"] * P + a.workspace_size(P)
+    if need(analysis) <= budget_bytes:
+        return analysis
+    for ch in (40, 20, 16, 10, 8, 5, 4, 2, 1):
+        if ch >= P:
+            continue
+        a2 = B.Analysis.from_system(system, **{**analysis.options, "selinv_chunk": ch})
+        if need(a2) <= budget_bytes:
+            return a2
+    raise B.PxsError("fit_to_budget", B.PXS_ENOMEM,
+                     f"{P} shifts need more than {budget_bytes / 2**30:.1f} GiB even one at a time")
+
+
 def options_for(system, P, cache=None, path=DEFAULT_CACHE):
     """Tuned analysis options for this system's bucket (defaults if the
     bucket has not been tuned)."""

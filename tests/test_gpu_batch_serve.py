@@ -1,14 +1,24 @@
-"""GPU tests of batched (uneven multi-system) execution and of the serving
-loop: results do not depend on batching, streams, residency or chunking."""
+"""GPU tests of batched (uneven multi-system) execution, graph plans and the
+serving loop: every result equals the oracle's density matrix entry by entry
+(the bar of the eager parity tests: |x - y| / max(|y|, 1e-3 max|y|) <= 1e-10,
+traces within 1e-10 relative, inertia counts exact), and results do not
+depend on batching, streams, residency or chunking (bit for bit where the
+same kernels run in the same order)."""
+import dataclasses
 import sys
 
 import numpy as np
 import pytest
 
+from oracle import dense as odense
+from oracle import hermitian as oherm
+from oracle import poles as opoles
 from paper_1405_0194_amd import lattice
 
 pytestmark = pytest.mark.gpu
 BETA = lattice.BETA_300K
+TOL = 1e-10
+SETNAMES = ("rho", "E", "F", "d")
 
 
 def say(*a):
@@ -24,12 +34,71 @@ def torch_cuda():
     return torch
 
 
-def _alone(torch, system, mu, P, nsets=2):
+_EIG = {}
+
+
+def _eig(system):
+    """Generalised eigenpairs of the pencil, cached per value arrays; the
+    cache holds the arrays themselves, so their ids cannot be reused by
+    other arrays while an entry exists."""
+    k = (id(system.hval), id(system.sval))
+    hit = _EIG.get(k)
+    if hit is None or hit[0] is not system.hval or hit[1] is not system.sval:
+        Hd, Sd = system.dense()
+        eig = oherm.gen_eigh(Hd, Sd) if system.hermitian else odense.gen_eigh(Hd, Sd)
+        hit = (system.hval, system.sval, Hd, Sd, eig)
+        _EIG[k] = hit
+    return hit[2:]
+
+
+def assert_oracle(system, mu, P, dE, out, traces, nsets=2, what=""):
+    """out (nsets, nnz) and traces (nsets, 2) of the HIP path against the
+    oracle's eigenbasis route with its own pole table.
+
+    Per-entry error |x - y| / max(|y|, 1e-3 scale).  For Gamma^rho the scale
+    is max|Gamma^rho|.  The energy set's weights are omega^E_l = (z_l + mu)
+    omega^rho_l-like, |z_l + mu| <= Delta E, so the terms it sums are up to
+    Delta E times those of Gamma^rho and its rounding error scales with
+    Delta E max|Gamma^rho|: that is its scale when it exceeds max|Gamma^E|
+    (a spectrum much narrower than Delta E makes Gamma^E itself small)."""
+    Hd, Sd, eig = _eig(system)
+    names = SETNAMES[:nsets]
+    ow, oom = opoles.pole_table(BETA, dE, mu, P, sets=names)
+    if system.hermitian:
+        G = oherm.gamma_route_b(Hd, Sd, ow, oom, eig=eig)
+        trf = oherm.traces
+    else:
+        G = odense.gamma_route_b(Hd, Sd, ow, oom, eig=eig)
+        trf = odense.traces
+    cols = system.entry_cols()
+    out = np.asarray(out)
+    rho_max = float(np.max(np.abs(G["rho"][system.rowind, cols])))
+    for g, name in enumerate(names):
+        y = G[name][system.rowind, cols]
+        scale = float(np.max(np.abs(y)))
+        if name == "E":
+            scale = max(scale, dE * rho_max)
+        e = float(np.max(np.abs(out[g] - y) / np.maximum(np.abs(y), 1e-3 * scale)))
+        tS, tH = trf(G[name], Hd, Sd)
+        say(f"  oracle {what} {system.kind} N={system.n} P={P} {name}: worst entry error {e:.2e}")
+        assert e <= TOL, (what, name, e)
+        assert abs(traces[g][0] - tS) <= TOL * max(1.0, abs(tS)), (what, name, traces[g][0], tS)
+        assert abs(traces[g][1] - tH) <= TOL * max(1.0, abs(tH)), (what, name, traces[g][1], tH)
+
+
+def assert_counts(system, eps, neg):
+    _, _, eig = _eig(system)
+    ev = np.sort(eig[0])
+    want = np.array([odense.inertia_count(ev, e) for e in eps])
+    assert np.array_equal(np.asarray(neg), want), (neg, want)
+
+
+def _alone(torch, system, mu, P, dE, nsets=2):
     from paper_1405_0194_amd import binding as B
     a = B.Analysis.from_system(system)
     H = torch.from_numpy(system.hval).to("cuda")
     S = torch.from_numpy(system.sval).to("cuda")
-    out, tr, info, _, _ = B.density_matrix(a, H, S, BETA, 1.0 + abs(mu), mu, P, nsets=nsets)
+    out, tr, info, _, _ = B.density_matrix(a, H, S, BETA, dE, mu, P, nsets=nsets)
     torch.cuda.synchronize()
     return out.cpu().numpy(), tr
 
@@ -44,7 +113,7 @@ def _small_mix(seed=1):
     ]
 
 
-def test_batch_runner_equals_individual_runs(torch_cuda):
+def test_batch_runner_equals_individual_runs_and_oracle(torch_cuda):
     torch = torch_cuda
     from paper_1405_0194_amd.batch import BatchRunner, Job
     mix = _small_mix()
@@ -53,13 +122,33 @@ def test_batch_runner_equals_individual_runs(torch_cuda):
     br = BatchRunner(jobs, budget_bytes=8 * 2**30, nstreams=3, keep_outputs=True)
     br.run()
     for j in jobs:
-        out, tr = _alone(torch, j.system, j.mu, j.poles)
-        assert np.array_equal(j.out.cpu().numpy(), out), j.system.kind
-        assert np.array_equal(j.traces, tr)
+        got = j.out.cpu().numpy()
         assert np.all(j.info == 0)
+        assert_oracle(j.system, j.mu, j.poles, j.dE, got, j.traces, what="batch")
+        out, tr = _alone(torch, j.system, j.mu, j.poles, j.dE)
+        assert np.array_equal(got, out), j.system.kind
+        assert np.array_equal(j.traces, tr)
 
 
-def test_server_results_alone_equal_results_in_mix(torch_cuda):
+def test_uneven_batch_sample_against_oracle(torch_cuda):
+    """Six systems of the 64-system uneven batch (two of each kind, N up to
+    1,950, 40-70 poles), run together through the batch runner with the
+    tuned analyses the benchmark uses; every result against the oracle."""
+    from paper_1405_0194_amd import tune
+    from paper_1405_0194_amd.batch import BatchRunner, Job
+    pick = {6, 7, 9, 26, 28, 41}
+    items = lattice.batch_systems(only=pick)
+    jobs = [Job(system=s, poles=P, mu=0.0) for s, P in items]
+    say("case: uneven batch sample", [(j.system.kind, j.system.n, j.poles) for j in jobs])
+    br = BatchRunner(jobs, budget_bytes=32 * 2**30, nstreams=4, keep_outputs=True,
+                     tuned=tune.load_cache() or None)
+    br.run()
+    for j in jobs:
+        assert np.all(j.info == 0)
+        assert_oracle(j.system, j.mu, j.poles, j.dE, j.out.cpu().numpy(), j.traces, what="uneven batch")
+
+
+def test_server_results_alone_equal_results_in_mix_and_oracle(torch_cuda):
     torch = torch_cuda
     from paper_1405_0194_amd.serve import Request, Server, poisson_arrivals
     mix = _small_mix(seed=7)
@@ -72,7 +161,6 @@ def test_server_results_alone_equal_results_in_mix(torch_cuda):
     for k in (0, 2, 2):
         s, P, mu = mix[k]
         hv = s.hval * (1.0 + 1e-3 * rng.standard_normal(s.nnz_lower))
-        import dataclasses
         reqs.append(Request(system=dataclasses.replace(s, hval=hv), mu=mu + 0.005, poles=P))
     arr = poisson_arrivals(len(reqs), rate=200.0, seed=5)
     for q, t in zip(reqs, arr):
@@ -84,15 +172,14 @@ def test_server_results_alone_equal_results_in_mix(torch_cuda):
     assert summary["symbolic_hits"] >= 3
     assert summary["plan_hits"] >= 1
     for q in reqs:
-        out, tr = _alone(torch, q.system, q.mu, q.poles)
-        assert np.array_equal(q.out.cpu().numpy(), out), q.rid
+        got = q.out.cpu().numpy()
+        assert np.all(q.info == 0)
+        assert_oracle(q.system, q.mu, q.poles, q.dE, got, q.traces, what=f"served request {q.rid}")
+        out, tr = _alone(torch, q.system, q.mu, q.poles, q.dE)
+        assert np.array_equal(got, out), q.rid
         assert np.array_equal(q.traces, tr), q.rid
         if q.eps is not None:
-            from paper_1405_0194_amd import binding as B
-            a = B.Analysis.from_system(q.system)
-            neg, _ = B.inertia(a, torch.from_numpy(q.system.hval).to("cuda"),
-                               torch.from_numpy(q.system.sval).to("cuda"), q.eps)
-            assert np.array_equal(q.neg_counts, neg)
+            assert_counts(q.system, q.eps, q.neg_counts)
 
 
 def test_server_chunks_a_request_larger_than_the_budget(torch_cuda):
@@ -104,22 +191,59 @@ def test_server_chunks_a_request_larger_than_the_budget(torch_cuda):
     a = B.Analysis.from_system(s)
     budget = resident_bytes(a, 12, 2) + 1024      # fits 12 of the 40 shifts
     srv = Server(budget_bytes=budget, nstreams=2, keep_outputs=True)
-    req = Request(system=s, mu=0.0, poles=P)
+    eps = np.array([-0.05, 0.0, 0.07])
+    req = Request(system=s, mu=0.0, poles=P, eps=eps)
     say("case: chunked request, budget", budget)
     srv.run([req], realtime=False)
     assert req.chunks > 1
-    out, tr = _alone(torch, s, 0.0, P)
+    out, tr = _alone(torch, s, 0.0, P, req.dE)
     got = req.out.cpu().numpy()
     assert np.max(np.abs(got - out)) <= 1e-12 * np.max(np.abs(out))
     assert np.allclose(req.traces, tr, rtol=1e-12, atol=1e-12)
+    assert np.all(req.info == 0)
+    assert_oracle(s, 0.0, P, req.dE, got, req.traces, what="chunked request")
+    assert_counts(s, eps, req.neg_counts)
 
 
-def _alone_hermitian(torch, system, mu, P, analysis=None, nsets=2):
+def test_graph_plan_replays_match_eager_and_oracle(torch_cuda):
+    """The captured graph replayed several times (with eager library work and
+    synchronisations in between, new pole tables and new H values) gives the
+    eager result bit for bit every time, and the oracle's."""
+    torch = torch_cuda
+    from paper_1405_0194_amd import binding as B
+    s = lattice.make_system("honeycomb", (6, 5), 13, 3.0, 31)
+    a = B.Analysis.from_system(s)
+    H = torch.from_numpy(s.hval).cuda()
+    S = torch.from_numpy(s.sval).cuda()
+    P = 20
+    say("case: graph plan replays")
+    plan = B.Plan(a, H, S, P, nsets=2)
+    rng = np.random.default_rng(2)
+    cur = s
+    for rep in range(4):
+        mu = float(rng.uniform(-0.1, 0.1))
+        if rep == 2:
+            cur = dataclasses.replace(s, hval=s.hval * (1.0 + 1e-3 * rng.standard_normal(s.nnz_lower)))
+            H.copy_(torch.from_numpy(cur.hval).cuda())
+        dE = 1.0 + abs(mu)
+        sh, wt = B.poles(BETA, dE, mu, P, 2)
+        out_g, tr_g, info = plan.run(sh, wt)
+        out_g = out_g.cpu().numpy().copy()
+        out_e, tr_e, info_e, _, _ = B.density_matrix(a, H, S, BETA, dE, mu, P, nsets=2)
+        torch.cuda.synchronize()
+        assert np.array_equal(out_g, out_e.cpu().numpy()), rep
+        assert np.array_equal(tr_g, tr_e), rep
+        assert np.all(info == 0)
+        if rep in (0, 2):
+            assert_oracle(cur, mu, P, dE, out_g, tr_g, what=f"plan replay {rep}")
+
+
+def _alone_hermitian(torch, system, mu, P, dE, analysis=None, nsets=2):
     from paper_1405_0194_amd import binding as B
     a = analysis if analysis is not None else B.Analysis.from_system(system)
     H = torch.from_numpy(system.hval).to("cuda")
     S = torch.from_numpy(system.sval).to("cuda")
-    sh, wt = B.poles(BETA, 1.0 + abs(mu), mu, P, nsets)
+    sh, wt = B.poles(BETA, dE, mu, P, nsets)
     f = B.HermitianFactorization(a, H, S, sh)
     f.selinv()
     out, tr = f.pole_sum(wt)
@@ -127,10 +251,11 @@ def _alone_hermitian(torch, system, mu, P, analysis=None, nsets=2):
     return out.cpu().numpy(), tr
 
 
-def test_hermitian_plan_replays_match_eager(torch_cuda):
+def test_hermitian_plan_replays_match_eager_and_oracle(torch_cuda):
     """The captured L D U + two-sided SelInv + pole sums, replayed with new
     pole tables and new H values (eager library work in between), equal the
-    eager Hermitian runs bit for bit every time."""
+    eager Hermitian runs bit for bit every time, and the oracle's
+    (M - M^H)/2i."""
     torch = torch_cuda
     from paper_1405_0194_amd import binding as B
     s = lattice.make_hermitian_system("honeycomb", (6, 5), 13, 3.0, 91)
@@ -141,11 +266,14 @@ def test_hermitian_plan_replays_match_eager(torch_cuda):
     say("case: hermitian graph plan replays")
     plan = B.Plan(a, H, S, P, nsets=2)
     rng = np.random.default_rng(3)
+    cur = s
     for rep in range(4):
         mu = float(rng.uniform(-0.1, 0.1))
         if rep == 2:
-            H.copy_(torch.from_numpy(s.hval * (1.0 + 1e-3 * rng.standard_normal(s.nnz_lower))).cuda())
-        sh, wt = B.poles(BETA, 1.0 + abs(mu), mu, P, 2)
+            cur = dataclasses.replace(s, hval=s.hval * (1.0 + 1e-3 * rng.standard_normal(s.nnz_lower)))
+            H.copy_(torch.from_numpy(cur.hval).cuda())
+        dE = 1.0 + abs(mu)
+        sh, wt = B.poles(BETA, dE, mu, P, 2)
         out_g, tr_g, info = plan.run(sh, wt)
         out_g = out_g.cpu().numpy().copy()
         f = B.HermitianFactorization(a, H, S, sh)
@@ -155,12 +283,14 @@ def test_hermitian_plan_replays_match_eager(torch_cuda):
         assert np.array_equal(out_g, out_e.cpu().numpy()), rep
         assert np.array_equal(tr_g, tr_e), rep
         assert np.all(info == 0)
+        if rep in (0, 2):
+            assert_oracle(cur, mu, P, dE, out_g, tr_g, what=f"hermitian plan replay {rep}")
 
 
-def test_batch_with_kpoints_equals_individual_runs(torch_cuda):
+def test_batch_with_kpoints_equals_individual_runs_and_oracle(torch_cuda):
     """Real systems and four Hermitian 'k-points' (one pattern, one shared
     analysis, different values) in one batch on 3 streams: every result
-    equals its run alone."""
+    equals its run alone and the oracle's."""
     torch = torch_cuda
     from paper_1405_0194_amd import binding as B
     from paper_1405_0194_amd.batch import BatchRunner, Job
@@ -174,10 +304,12 @@ def test_batch_with_kpoints_equals_individual_runs(torch_cuda):
     br = BatchRunner(jobs, budget_bytes=16 * 2**30, nstreams=3, keep_outputs=True)
     br.run()
     for j in jobs:
-        if np.iscomplexobj(j.system.hval):
-            out, tr = _alone_hermitian(torch, j.system, j.mu, j.poles, analysis=shared)
+        got = j.out.cpu().numpy()
+        if j.system.hermitian:
+            out, tr = _alone_hermitian(torch, j.system, j.mu, j.poles, j.dE, analysis=shared)
         else:
-            out, tr = _alone(torch, j.system, j.mu, j.poles)
-        assert np.array_equal(j.out.cpu().numpy(), out), j.system.kind
+            out, tr = _alone(torch, j.system, j.mu, j.poles, j.dE)
+        assert np.array_equal(got, out), j.system.kind
         assert np.array_equal(j.traces, tr)
         assert np.all(j.info == 0)
+        assert_oracle(j.system, j.mu, j.poles, j.dE, got, j.traces, what="k-point batch")

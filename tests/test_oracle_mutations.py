@@ -111,6 +111,13 @@ def _mutations():
          lambda f: (lambda eig, eps, eta: f(eig, eps, eta) * (np.pi / 2.0)),
          [(t_dos.test_ldos_routes_agree_and_trace_is_broadened_dos, (0.13, 1e-3)),
           (t_dos.test_broadened_dos_tends_to_bin_counts, ())]),
+        ("permutation applied as its inverse", symbolic, "permute",
+         lambda f: (lambda P, perm: f(P, np.argsort(perm))),
+         [(t_symb.test_permute_is_the_permutation_similarity, ())]),
+        ("permutation applied to the rows only", symbolic, "permute",
+         lambda f: (lambda P, perm: P[perm]),
+         [(t_symb.test_permute_is_the_permutation_similarity, ()),
+          (t_symb.test_permute_reversed_arrow_fills_completely, ())]),
         ("symbolic factor without fill", symbolic, "fill_pattern",
          lambda f: (lambda P: (lambda L: (np.fill_diagonal(L, True), L)[1])(np.tril(P.copy()))),
          [(t_symb.test_matches_numeric_cholesky_pattern, ()), (t_symb.test_arrow_matrices, ())]),

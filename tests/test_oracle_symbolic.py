@@ -60,3 +60,37 @@ def test_matches_numeric_cholesky_pattern():
         for j in range(n):
             below = [i for i in range(j + 1, n) if L[i, j]]
             assert par[j] == (below[0] if below else -1)
+
+
+def test_permute_is_the_permutation_similarity():
+    """permute(P, perm) = Q^T P Q with Q the permutation matrix whose column
+    `new` is e_perm[new] (an integer matrix product, not the oracle's
+    indexing)."""
+    rng = np.random.default_rng(11)
+    n = 9
+    P = rng.uniform(size=(n, n)) < 0.3
+    P = P | P.T
+    perm = rng.permutation(n)
+    Q = np.zeros((n, n), dtype=np.int64)
+    Q[perm, np.arange(n)] = 1
+    want = (Q.T @ P.astype(np.int64) @ Q) != 0
+    assert np.array_equal(symbolic.permute(P, perm), want)
+    # the inverse permutation undoes it
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    assert np.array_equal(symbolic.permute(symbolic.permute(P, perm), inv), P)
+
+
+def test_permute_reversed_arrow_fills_completely():
+    """A bottom arrow (full last row and column) has no fill in natural
+    order; reversed (perm[new] = n - 1 - new) it is a top arrow, whose first
+    elimination step connects every pair, so L is completely full."""
+    n = 8
+    P = np.eye(n, dtype=bool)
+    P[-1, :] = True
+    P[:, -1] = True
+    L0 = symbolic.fill_pattern(P)
+    assert np.array_equal(L0, np.tril(P))
+    R = symbolic.permute(P, np.arange(n)[::-1])
+    assert R[0].all() and R[:, 0].all() and R[1:, 1:].sum() == n - 1
+    assert np.array_equal(symbolic.fill_pattern(R), np.tril(np.ones((n, n), dtype=bool)))
