@@ -262,6 +262,24 @@ pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double
                               int64_t* info, pxs_c64* shifts, pxs_c64* weights,
                               void* stream);
 
+/* Allocation-free variant of pxs_density_matrix, for callers that cannot
+ * allocate device memory (tight serving loops, code that must not call
+ * hipMalloc): the same computation and results (bit for bit), with the
+ * workspace in a device array inside the library (64 MiB per device, held
+ * until the process ends) instead of a caller buffer.  The caller still
+ * passes the bound symbolic handle, H and S values, Lbuf (P *
+ * bytes_per_shift bytes) and out (device nsets * nnz_lower doubles).
+ * Every launch runs on `stream` (no library streams); the call synchronises
+ * it.  Calls on one device share the array: calls that overlap in time on
+ * one device (several host threads or streams) race and must be serialised
+ * by the caller.  Errors: PXS_EINVAL, before any device work, when the
+ * system and P need more workspace than the array holds (pxs_last_error
+ * gives both sizes), and for the arguments pxs_density_matrix rejects. */
+pxs_status pxs_density_matrix_noalloc(pxs_symbolic sym, const double* Hval, const double* Sval,
+                                      double beta, double dE, double mu, int32_t P, int32_t nsets,
+                                      void* Lbuf, double* out, double* traces, int64_t* info,
+                                      pxs_c64* shifts, pxs_c64* weights, void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Graph-captured density matrix (the batched execution of all shifts as one
  * replayable HIP graph).  pxs_plan_create captures assembly, LDL^T, selected

@@ -80,6 +80,8 @@ def load():
         "pxs_inertia_hermitian": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
         "pxs_density_matrix": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
                                          C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
+        "pxs_density_matrix_noalloc": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
+                                                 C.c_int32, _P, _P, _P, _P, _P, _P, _P]),
         "pxs_plan_create": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P]),
         "pxs_plan_create_hermitian": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P]),
         "pxs_plan_run": (C.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -540,6 +542,33 @@ def density_matrix(analysis: Analysis, H, S, beta, dE, mu, P, nsets=2, L=None, w
                                   _dptr(work), _dptr(out), _ptr(tr), _ptr(info), _ptr(sh), _ptr(wt),
                                   _stream(stream))
     _check("pxs_density_matrix", code, allow=(PXS_OK, PXS_TINY_PIVOT))
+    return out.view(nsets, nnz), tr.reshape(nsets, 2), info, sh, wt.reshape(nsets, P)
+
+
+def density_matrix_noalloc(analysis: Analysis, H, S, beta, dE, mu, P, nsets=2, L=None, out=None,
+                           stream=None):
+    """pxs_density_matrix_noalloc: the fused density matrix with the
+    workspace in the library's device scratch array (no workspace
+    argument).  L and out are caller buffers as for density_matrix.
+    Returns (out (nsets, nnz), traces (nsets, 2), info, shifts, weights)."""
+    import torch
+    lib = load()
+    analysis.bind()
+    nnz = analysis.info["nnz_lower"]
+    if L is None:
+        L = torch.empty(P * analysis.info["bytes_per_shift"], dtype=torch.uint8, device=H.device)
+    if out is None:
+        out = torch.empty(nsets * nnz, dtype=torch.float64, device=H.device)
+    _require_values(analysis, H, S)
+    _require(L, P * analysis.info["bytes_per_shift"], "factor storage")
+    _require(out, 8 * nsets * nnz, "pole-sum output")
+    tr = np.zeros(2 * nsets)
+    info = np.zeros(P, dtype=np.int64)
+    sh = np.zeros(P, dtype=np.complex128)
+    wt = np.zeros(nsets * P, dtype=np.complex128)
+    code = lib.pxs_density_matrix_noalloc(analysis._h, _dptr(H), _dptr(S), beta, dE, mu, P, nsets, _dptr(L),
+                                          _dptr(out), _ptr(tr), _ptr(info), _ptr(sh), _ptr(wt), _stream(stream))
+    _check("pxs_density_matrix_noalloc", code, allow=(PXS_OK, PXS_TINY_PIVOT))
     return out.view(nsets, nnz), tr.reshape(nsets, 2), info, sh, wt.reshape(nsets, P)
 
 

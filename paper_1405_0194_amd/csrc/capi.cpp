@@ -438,6 +438,54 @@ pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double
   return piv;
 }
 
+pxs_status pxs_density_matrix_noalloc(pxs_symbolic sym, const double* Hval, const double* Sval, double beta,
+                                      double dE, double mu, int32_t P, int32_t nsets, void* Lbuf, double* out,
+                                      double* traces, int64_t* info, pxs_c64* shifts, pxs_c64* weights,
+                                      void* stream) {
+  if (!sym || nsets < 1 || nsets > 4 || P < 2 || (P & 1) || P > pxs::MAX_SHIFTS) return PXS_EINVAL;
+  const pxs::Symbolic& S = sym->S;
+  // the size limit is checked before anything touches the device
+  const int64_t need = pxs::selinv_work_bytes_inorder(S, P);
+  if (need > pxs::NOALLOC_SCRATCH_BYTES) {
+    g_last_error = "pxs_density_matrix_noalloc: this system and pole count need " + std::to_string(need) +
+                   " bytes of workspace; the library's scratch array holds " +
+                   std::to_string(pxs::NOALLOC_SCRATCH_BYTES) + " (use pxs_density_matrix with a workspace)";
+    return PXS_EINVAL;
+  }
+  if (!Hval || !Sval || !Lbuf || !out || !aligned256(Lbuf)) return PXS_EINVAL;
+  if (!S.dmaps) return PXS_ESTATE;
+  std::vector<pxs_c64> sh(P), wt((size_t)nsets * P);
+  pxs_status s = pxs_poles(beta, dE, mu, P, nsets, sh.data(), wt.data());
+  if (s != PXS_OK) return s;
+  void* work = nullptr;
+  int e = pxs::noalloc_scratch(&work);
+  if (e != 0) return hip_fail(e);
+  hipStream_t st = (hipStream_t)stream;
+  // every launch on the caller's stream: no library streams or events
+  e = pxs::run_factor<true>(S, Hval, Sval, P, (const double*)sh.data(), Lbuf, work, st, true);
+  if (e == 0) e = pxs::run_selinv(S, P, Lbuf, work, st, nullptr, true);
+  if (e == 0) e = pxs::run_pole_sum(S, P, Lbuf, work, Hval, Sval, nsets, (const double*)wt.data(), out, st);
+  if (e != 0) return hip_fail(e);
+  // the shift and weight uploads read sh and wt: finish before they go
+  double t8[8];
+  std::vector<int64_t> inf(P);
+  hipError_t he = hipMemcpyAsync(t8, (char*)work + pxs::WK_TRACES, sizeof(t8), hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(inf.data(), (char*)work + pxs::WK_INFO, sizeof(int64_t) * P, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(he);
+  if (traces)
+    for (int g = 0; g < 2 * nsets; ++g) traces[g] = t8[g];
+  bool tiny = false;
+  for (int32_t l = 0; l < P; ++l) {
+    if (info) info[l] = inf[l];
+    tiny = tiny || inf[l] != 0;
+  }
+  if (shifts) std::memcpy(shifts, sh.data(), sizeof(pxs_c64) * P);
+  if (weights) std::memcpy(weights, wt.data(), sizeof(pxs_c64) * nsets * P);
+  return tiny ? PXS_TINY_PIVOT : PXS_OK;
+}
+
 // One capture for both kinds of pencil: herm selects the L D U kernels (no
 // accumulation into out for those).
 static pxs_status plan_create(pxs_symbolic sym, const double* Hval, const double* Sval, int32_t nshift,

@@ -28,14 +28,16 @@ enum KernelClass { KC_NONE = 0, KC_UPDATE = 1, KC_SELINV_OFF = 2, KC_TRSM = 3, K
 int profile_begin(int kernel);
 int profile_end(double* ms, int64_t* launches, double* work, double* bytes, double* stored);
 
+// inorder: every launch on the caller's stream (no library streams), as
+// inside a stream capture; the results are the same bits either way.
 template <bool CPLX>
 int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
-               const double* shifts_host, void* L, void* work, hipStream_t st);
+               const double* shifts_host, void* L, void* work, hipStream_t st, bool inorder = false);
 // Kernel-only parts (no host copies), capturable into a HIP graph; the
 // shifts and weights are read from the workspace.
 template <bool CPLX>
 int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int nshift, void* L,
-                       void* work, hipStream_t st);
+                       void* work, hipStream_t st, bool inorder = false);
 int run_pole_sum_kernels(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
                          const double* Sv, int nsets, double* out, int accumulate, hipStream_t st);
 int upload_shifts(int nshift, const double* shifts_host, void* work, hipStream_t st);
@@ -43,12 +45,21 @@ int upload_weights(int nshift, int nsets, const double* weights_host, void* work
 // events: nullptr (library pool) or selinv_event_count(S) events owned by
 // the caller (a graph plan).
 int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st,
-               hipEvent_t* events = nullptr);
+               hipEvent_t* events = nullptr, bool inorder = false);
 int selinv_event_count(const Symbolic& S);
 // creates the subtree streams (call outside any stream capture)
 int selinv_streams_ready(const Symbolic& S);
 // workspace bytes a batch of nshift complex shifts needs (factor + SelInv)
 int64_t selinv_work_bytes(const Symbolic& S, int nshift);
+// the same when every launch runs on one stream (inorder, or a capture)
+int64_t selinv_work_bytes_inorder(const Symbolic& S, int nshift);
+
+// Workspace of the allocation-free density matrix: a device array of this
+// size in the library's code object (one per device, for the life of the
+// process), shared by every call on that device.
+constexpr int64_t NOALLOC_SCRATCH_BYTES = int64_t(64) << 20;
+// Its device address on the current device (looked up once per device).
+int noalloc_scratch(void** ptr);
 int run_pole_sum(const Symbolic& S, int nshift, const void* L, void* work, const double* H,
                  const double* Sv, int nsets, const double* weights_host, double* out,
                  hipStream_t st);

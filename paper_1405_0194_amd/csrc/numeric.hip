@@ -1249,10 +1249,10 @@ int upload_weights(int nshift, int nsets, const double* weights_host, void* work
 
 template <bool CPLX>
 int run_factor(const Symbolic& S, const double* H, const double* Sv, int nshift,
-               const double* shifts_host, void* L, void* work, hipStream_t st) {
+               const double* shifts_host, void* L, void* work, hipStream_t st, bool inorder) {
   int e = upload_shifts(nshift, shifts_host, work, st);
   if (e != 0) return e;
-  return run_factor_kernels<CPLX>(S, H, Sv, nshift, L, work, st);
+  return run_factor_kernels<CPLX>(S, H, Sv, nshift, L, work, st, inorder);
 }
 
 // Streams and events owned by the library for the subtree-parallel
@@ -1291,7 +1291,7 @@ int ensure_pool(int nstreams, int nevents) {
 
 template <bool CPLX>
 int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int nshift, void* L,
-                       void* work, hipStream_t st) {
+                       void* work, hipStream_t st, bool inorder) {
   char* w = (char*)work;
   hipLaunchKernelGGL(k_zero_i64, dim3((2 * MAX_SHIFTS + NT - 1) / NT), dim3(NT), 0, st,
                      (int64_t*)(w + WK_INFO), 2 * MAX_SHIFTS);
@@ -1392,7 +1392,7 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
   hipError_t he = hipStreamIsCapturing(st, &cap);
   if (he != hipSuccess) return (int)he;
   int err = 0;
-  if (cap != hipStreamCaptureStatusNone || NS <= 1) {
+  if (cap != hipStreamCaptureStatusNone || NS <= 1 || inorder) {
     for (int J : S.fac_order) {
       if (pfirst[J] < 0) continue;
       for (int ip = pfirst[J]; ip <= plast[J]; ++ip)
@@ -1431,16 +1431,51 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
   return 0;
 }
 
-template int run_factor<true>(const Symbolic&, const double*, const double*, int, const double*, void*, void*, hipStream_t);
-template int run_factor<false>(const Symbolic&, const double*, const double*, int, const double*, void*, void*, hipStream_t);
-template int run_factor_kernels<true>(const Symbolic&, const double*, const double*, int, void*, void*, hipStream_t);
-template int run_factor_kernels<false>(const Symbolic&, const double*, const double*, int, void*, void*, hipStream_t);
+template int run_factor<true>(const Symbolic&, const double*, const double*, int, const double*, void*, void*,
+                              hipStream_t, bool);
+template int run_factor<false>(const Symbolic&, const double*, const double*, int, const double*, void*, void*,
+                               hipStream_t, bool);
+template int run_factor_kernels<true>(const Symbolic&, const double*, const double*, int, void*, void*, hipStream_t,
+                                      bool);
+template int run_factor_kernels<false>(const Symbolic&, const double*, const double*, int, void*, void*,
+                                       hipStream_t, bool);
 
 int64_t selinv_work_bytes(const Symbolic& S, int nshift) {
   const int chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
   int64_t g = 0;
   for (int64_t b : S.gather_bytes) g += b;
   return S.work_fixed + (int64_t)nshift * S.sel_nstreams * S.work_per_shift + (int64_t)chunk * g;
+}
+
+int64_t selinv_work_bytes_inorder(const Symbolic& S, int nshift) {
+  const int chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
+  return S.work_fixed + (int64_t)nshift * S.work_per_shift + (int64_t)chunk * S.gather_per_shift;
+}
+
+// Workspace of the allocation-free entry point (pxs_density_matrix_noalloc).
+// Host code never passes this name to a kernel or a copy: it stands for a
+// host-side shadow there; the device address comes from noalloc_scratch.
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+int noalloc_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (dev < 0 || dev >= MAX_DEVICES) return (int)hipErrorInvalidDevice;
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!p) return (int)hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return 0;
 }
 
 #define PXS_HIP(call)                      \
@@ -1457,33 +1492,35 @@ int selinv_streams_ready(const Symbolic& S) {
 int selinv_event_count(const Symbolic& S) { return S.nsuper + S.sel_nstreams + 1; }
 
 int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st,
-               hipEvent_t* events) {
+               hipEvent_t* events, bool inorder) {
   // inside a stream capture everything runs on the capturing stream: the
   // subtree streams are used by eager runs only
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   PXS_HIP(hipStreamIsCapturing(st, &cap));
-  const bool single = (cap != hipStreamCaptureStatusNone) || S.sel_nstreams == 1;
+  const bool single = inorder || (cap != hipStreamCaptureStatusNone) || S.sel_nstreams == 1;
   const int NS = single ? 1 : S.sel_nstreams;
   const int ns = S.nsuper;
   const int TR = S.tile_rows;
-  int err = ensure_pool(NS - 1, events ? 0 : selinv_event_count(S));
+  // one stream needs no pool: the in-order path creates no streams or events
+  int err = single ? 0 : ensure_pool(NS - 1, events ? 0 : selinv_event_count(S));
   if (err) return err;
   std::vector<hipStream_t> strm(NS);
   strm[0] = st;
   for (int q = 1; q < NS; ++q) strm[q] = g_pool.streams[q - 1];
   // events: the caller's (a graph plan keeps its own, since an event last
-  // recorded inside a capture must not be waited on outside it) or the pool's
-  hipEvent_t* ev = events ? events : g_pool.events.data();   // ev[J]: SelInv of J done
-  hipEvent_t* ev_join = ev + ns;                   // ev_join[q], q >= 1
-  hipEvent_t ev_fork = ev[ns + NS];
+  // recorded inside a capture must not be waited on outside it) or the
+  // pool's; none on one stream
+  hipEvent_t* ev = single ? nullptr : (events ? events : g_pool.events.data());   // ev[J]: SelInv of J done
+  hipEvent_t* ev_join = single ? nullptr : ev + ns;   // ev_join[q], q >= 1
+  hipEvent_t ev_fork = single ? nullptr : ev[ns + NS];
   const int chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
   // per-stream workspace views
   std::vector<Common> cs(NS, make_common(S, L, work));
   // workspace views (selinv_work_bytes): per-shift regions of all streams,
-  // then the dense Z_CC regions of all streams; one stream alone uses the
-  // first per-shift region and the whole Z_CC area with the largest stride
-  // (max_q gather_bytes[q] <= sum_q gather_bytes[q])
-  int64_t gofs = S.work_fixed + (int64_t)nshift * S.sel_nstreams * S.work_per_shift;
+  // then the dense Z_CC regions of all streams; one stream alone uses one
+  // per-shift region and a Z_CC area with the largest stride right after it
+  // (selinv_work_bytes_inorder <= selinv_work_bytes)
+  int64_t gofs = S.work_fixed + (int64_t)nshift * (single ? 1 : S.sel_nstreams) * S.work_per_shift;
   for (int q = 0; q < NS; ++q) {
     cs[q].wfix = S.work_fixed + (int64_t)q * nshift * S.work_per_shift;
     cs[q].G = (double*)((char*)work + gofs);
