@@ -31,7 +31,7 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 
 MULTI = {
     "batch": "64 uneven systems (chain / honeycomb / cubic, kind = s mod 3), N log-uniform in "
-             "[500, 8000], 40-80 poles each, graph-captured plans over 4 HIP streams, 250 GiB budget",
+             "[500, 8000], 40-80 poles each, 250 GiB budget",
     "serve": "Poisson request stream: sizes Zipf(1.2) over k*1000 basis functions, chain / honeycomb / "
              "cubic, 40 poles, 30% SCF-style repeats of a resident pattern, 16-shift inertia counts on "
              "new patterns, 250 GiB admission budget, 4 streams",
@@ -53,12 +53,18 @@ WORKLOADS = {
 }
 
 
+SOURCES_HASHED = ("numeric.hip", "batch.inc", "symbolic.cpp")
+
+
 def kernel_source_hash(text=None):
-    """Hash of the kernel source's code: comments and layout do not count, so
-    a counter summary stays valid across edits of comments only."""
+    """Hash of the code that sets a kernel's memory traffic (the kernels and
+    the symbolic layout of the factor storage): comments and layout do not
+    count, so a counter summary stays valid across edits of comments only."""
     if text is None:
-        with open(os.path.join(ROOT, "paper_1405_0194_amd", "csrc", "numeric.hip")) as f:
-            text = f.read()
+        text = ""
+        for name in SOURCES_HASHED:
+            with open(os.path.join(ROOT, "paper_1405_0194_amd", "csrc", name)) as f:
+                text += f.read()
     code = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
     code = re.sub(r"//[^\n]*", " ", code)
     code = " ".join(code.split())
@@ -114,9 +120,10 @@ def traffic_from_counters(kernel, workload, fetch_dir, write_dir, copy_fetch_dir
     print(json.dumps(out))
 
 
-def cpu_baseline(full_n, seconds_target=15.0):
+def cpu_baseline(full_n, seconds_target=10.0, cells=18):
     """The oracle as it stands: one pole-solve = dense inverse of H - w S.
-    Timed on a smaller honeycomb sample and scaled by (N_sample / N)^3."""
+    Timed on a honeycomb sample of 18 x 18 cells (N = 8,424) and scaled by
+    (N_sample / N)^3."""
     import numpy as np
     from oracle import dense
     from paper_1405_0194_amd import lattice
@@ -125,7 +132,6 @@ def cpu_baseline(full_n, seconds_target=15.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = len(os.sched_getaffinity(0))
-    cells = 10
     s = lattice.make_system("honeycomb", (cells, cells), 13, 3.0, 7)
     Hd, Sd = s.dense()
     w = 0.01 + 0.003j
@@ -135,7 +141,7 @@ def cpu_baseline(full_n, seconds_target=15.0):
         dense.shifted_inverse(Hd, Sd, w)
         reps += 1
         el = time.perf_counter() - t0
-        if el > seconds_target or reps >= 50:
+        if el > seconds_target or reps >= 20:
             break
     per = el / reps
     scale = (s.n / float(full_n)) ** 3
@@ -146,13 +152,12 @@ def cpu_baseline(full_n, seconds_target=15.0):
                        f"scaled by (N_sample/N)^3 to N={full_n}")}
 
 
-def cpu_eigh_baseline(full_n, reps=2):
+def cpu_eigh_baseline(full_n, reps=1, cells=18):
     """The dense-diagonalization route the method replaces: the oracle's
     generalized eigendecomposition of (H, S) (one per density matrix, any P),
-    timed on a smaller honeycomb sample and scaled by (N / N_sample)^3."""
+    timed on a honeycomb sample (N = 8,424) and scaled by (N / N_sample)^3."""
     from oracle import dense
     from paper_1405_0194_amd import lattice
-    cells = 10
     s = lattice.make_system("honeycomb", (cells, cells), 13, 3.0, 7)
     Hd, Sd = s.dense()
     t0 = time.perf_counter()
@@ -163,6 +168,44 @@ def cpu_eigh_baseline(full_n, reps=2):
             "sample": (f"{reps} generalized dense eigendecompositions (scipy eigh) of a honeycomb {cells}x{cells}x2 "
                        f"atoms x 13 orbitals pencil (N={s.n}), {per:.2f} s each, scaled by (N/N_sample)^3 to "
                        f"N={full_n}; the GPU path takes ms_per_step for one density matrix")}
+
+
+def chain_leg(reps=200):
+    """The chain workload (open 1D chain, 64 atoms x 4 orbitals, N = 256, 40
+    poles at 300 K): microseconds per density matrix through a replayed graph
+    plan (no host synchronisation between replays), through the eager fused
+    call and through the allocation-free call (both synchronise per call)."""
+    import torch
+    from paper_1405_0194_amd import binding as B
+    from paper_1405_0194_amd import lattice
+    s = lattice.config_system(0)
+    P, mu = lattice.CONFIG_POLES[0], 0.0
+    dE = 1.0 + abs(mu)
+    a = B.Analysis.from_system(s).bind()
+    H = torch.from_numpy(s.hval).cuda()
+    S = torch.from_numpy(s.sval).cuda()
+    plan = B.Plan(a, H, S, P, nsets=2)
+    sh, wt = B.poles(lattice.BETA_300K, dE, mu, P, 2)
+    L, W = a.buffers(P)
+
+    def timed(fn, n):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return 1e6 * (time.perf_counter() - t) / n
+
+    plan_us = timed(lambda: plan.run(sh, wt, sync=False), reps)
+    eager_us = timed(lambda: B.density_matrix(a, H, S, lattice.BETA_300K, dE, mu, P, nsets=2, L=L, work=W), reps // 4)
+    noalloc_us = timed(lambda: B.density_matrix_noalloc(a, H, S, lattice.BETA_300K, dE, mu, P, nsets=2, L=L),
+                       reps // 4)
+    return {"workload": WORKLOADS["chain"]["desc"], "graph_plan_us_per_density_matrix": round(plan_us, 1),
+            "graph_plan_pole_solves_per_s": round(P / (plan_us * 1e-6), 1),
+            "eager_us_per_density_matrix": round(eager_us, 1),
+            "noalloc_us_per_density_matrix": round(noalloc_us, 1), "replays": reps}
 
 
 def per_pole_sample(a, H, S, beta, dE, mu, P, nsample):
@@ -182,36 +225,55 @@ def per_pole_sample(a, H, S, beta, dE, mu, P, nsample):
 
 def run_batch(args):
     import torch
-    from paper_1405_0194_amd import lattice
+    from paper_1405_0194_amd import lattice, tune
     from paper_1405_0194_amd.batch import BatchRunner, Job
     t = time.perf_counter()
     items = lattice.batch_systems()
-    jobs = [Job(system=s, poles=P, mu=0.0) for s, P in items]
-    print(f"# batch: {len(jobs)} systems generated in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
-    from paper_1405_0194_amd import tune
+    print(f"# batch: {len(items)} systems generated in {time.perf_counter() - t:.1f}s", file=sys.stderr, flush=True)
     tuned = tune.load_cache() or None
-    br = BatchRunner(jobs, budget_bytes=250 * 2**30, nstreams=4, tuned=tuned)
-    for i in range(args.warmup):
-        print(f"# warmup {i}: {br.run():.2f}s", file=sys.stderr, flush=True)
-    times = []
-    for i in range(args.steps):
-        times.append(br.run())
-        print(f"# step {i}: {times[-1]:.2f}s", file=sys.stderr, flush=True)
-    elapsed = sum(times)
-    solves = br.total_solves() * args.steps
-    flops = br.total_flops() * args.steps
-    seq = BatchRunner(jobs, budget_bytes=250 * 2**30, nstreams=1, tuned=tuned)
-    t1 = seq.run()
-    print(f"# one stream: {t1:.2f}s", file=sys.stderr, flush=True)
+
+    def measure(mode, streams, groups, steps, warmup):
+        jobs = [Job(system=s, poles=P, mu=0.0) for s, P in items]
+        t_an = time.perf_counter()
+        br = BatchRunner(jobs, budget_bytes=250 * 2**30, nstreams=streams, tuned=tuned, mode=mode, groups=groups,
+                         alone_share=args.batch_alone_share)
+        t_an = time.perf_counter() - t_an
+        t_first = br.run()        # creates the plans or the fused graphs
+        print(f"# {mode} x{streams}: analyses {t_an:.1f}s, first run {t_first:.2f}s", file=sys.stderr, flush=True)
+        for i in range(max(0, warmup - 1)):
+            print(f"# {mode} warmup {i}: {br.run():.3f}s", file=sys.stderr, flush=True)
+        times = []
+        for i in range(steps):
+            times.append(br.run())
+            waves = getattr(br, "wave_seconds", None)
+            print(f"# {mode} step {i}: {times[-1]:.3f}s" + (f" waves {[round(w, 3) for w in waves]}" if waves else ""),
+                  file=sys.stderr, flush=True)
+        launches = br.fused_launches() if mode == "fused" else None
+        out = dict(solves=br.total_solves(), flops=br.total_flops(), times=times, first=t_first,
+                   launches=launches, info_ok=all(np.all(j.info == 0) for j in jobs))
+        del br, jobs
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return out
+
+    main = measure(args.batch_mode, args.batch_streams, args.batch_streams, args.steps, args.warmup)
+    alt_mode = "plans" if args.batch_mode == "fused" else "fused"
+    alt = measure(alt_mode, 4, 4, max(1, args.steps // 2), args.warmup)
+    elapsed = sum(main["times"])
+    solves = main["solves"] * args.steps
+    flops = main["flops"] * args.steps
     res = dict(value=round(solves / elapsed, 4), ms_per_step=round(1e3 * elapsed / args.steps, 3),
                path_tflops=round(flops / elapsed / 1e12, 3),
                fp64_mfma_pct=round(100.0 * flops / elapsed / 1e12 / PEAK_FP64_TFLOPS, 2),
-               latency_s={"p50": round(float(np.percentile(times, 50)), 4),
-                          "p99": round(float(np.percentile(times, 99)), 4)},
-               one_stream_pole_solves_per_s=round(br.total_solves() / t1, 4),
-               config={"workload": MULTI["batch"], "systems": len(jobs), "pole_solves_per_step": br.total_solves(),
-                       "tflop_per_step": round(br.total_flops() / 1e12, 2),
-                       "tuned_buckets": len(tuned or {})})
+               latency_s={"p50": round(float(np.percentile(main["times"], 50)), 4),
+                          "p99": round(float(np.percentile(main["times"], 99)), 4)},
+               first_run_s=round(main["first"], 3), fused_launches=main["launches"],
+               all_info_zero=bool(main["info_ok"] and alt["info_ok"]),
+               comparison={f"{alt_mode}_4_streams_pole_solves_per_s":
+                           round(alt["solves"] * len(alt["times"]) / sum(alt["times"]), 4)},
+               config={"workload": MULTI["batch"], "systems": len(items), "mode": args.batch_mode,
+                       "streams": args.batch_streams, "pole_solves_per_step": main["solves"],
+                       "tflop_per_step": round(main["flops"] / 1e12, 2), "tuned_buckets": len(tuned or {})})
     return res
 
 
@@ -365,8 +427,9 @@ def main():
     ap.add_argument("--workload", default="honeycomb", choices=sorted(WORKLOADS) + sorted(MULTI))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-kernel", default="selinv_off")
-    ap.add_argument("--compare-perpole", type=int, default=0,
-                    help="also time the plain per-pole loop on this many shifts")
+    ap.add_argument("--compare-perpole", type=int, default=4,
+                    help="also time the plain per-pole loop on this many shifts (0: skip)")
+    ap.add_argument("--no-chain", action="store_true", help="skip the chain-workload leg")
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per tile of the panel products (64/128)")
     ap.add_argument("--panel-width", type=int, default=0)
     ap.add_argument("--leaf-cols", type=int, default=0)
@@ -379,6 +442,12 @@ def main():
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/<kernel>_<workload>_traffic.json from four rocprofv3 --pmc "
                          "output folders and exit (no GPU use)")
+    ap.add_argument("--batch-mode", default="plans", choices=("fused", "plans"),
+                    help="batch: one graph plan per system, or fused multi-system launches")
+    ap.add_argument("--batch-streams", type=int, default=4,
+                    help="batch: streams (fused: groups of systems per wave)")
+    ap.add_argument("--batch-alone-share", type=float, default=0.04,
+                    help="batch, fused: systems with at least this share of a wave's work run alone")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--kmax", type=int, default=16, help="serve: largest size class (k * 1000)")
     args = ap.parse_args()
@@ -498,7 +567,7 @@ def main():
         print(f"# step {i}: {lat[-1]:.3f}s  Tr(GS)={tr[0, 0]:.6f}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kms, klaunch, kwork, kbytes = B.profile_end(with_bytes=True)
+    kms, klaunch, kwork, kbytes, kstored = B.profile_end(with_bytes=True, with_stored=True)
 
     # phase breakdown on one extra (untimed) step
     phases = {}
@@ -524,12 +593,13 @@ def main():
         L1, W1 = (L, W1) if W1 is not None else a1.buffers(P)
         B.profile_begin(args.profile_kernel)
         B.density_matrix(a1, H, S, beta, dE, mu, P, nsets=2, L=L1, work=W1)
-        ims, il, iw = B.profile_end()
+        ims, il, iw, ist = B.profile_end(with_stored=True)
         if il:
             iavg = ims / il
             iach = (iw / il) / (iavg / 1e3) / 1e12
             iso = {"achieved": round(iach, 3), "frac": round(iach / PEAK_FP64_TFLOPS, 4),
-                   "avg_launch_ms": round(iavg, 4), "launches": il}
+                   "avg_launch_ms": round(iavg, 4), "launches": il,
+                   "stored_achieved": round((ist / il) / (iavg / 1e3) / 1e12, 3)}
         del a1
 
     # achieved HBM rate of the memory-bound kernels (assembly, pole sum, Z_CC
@@ -577,6 +647,10 @@ def main():
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                      "avg_launch_ms": round(avg_ms, 4), "launches": klaunch,
+                     "flops_per_launch": round(kwork / max(klaunch, 1)),
+                     "stored_flops_per_launch": round(kstored / max(klaunch, 1)),
+                     "stored_achieved": round((kstored / max(klaunch, 1)) / (avg_ms / 1e3) / 1e12, 3)
+                     if klaunch else 0.0,
                      "traffic": traffic,
                      "algorithmic_bytes_per_launch": round(kbytes / max(klaunch, 1)),
                      "isolated": iso},
@@ -585,6 +659,8 @@ def main():
         gbs = (kwork / max(klaunch, 1)) / (avg_ms / 1e3) / 1e9 if klaunch else 0.0
         res["roofline"].update({"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                                 "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)})
+    if not args.no_chain:
+        res["chain"] = chain_leg()
     if args.compare_perpole:
         del f
         sec = per_pole_sample(a, H, S, beta, dE, mu, P, args.compare_perpole)

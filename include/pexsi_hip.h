@@ -242,6 +242,19 @@ pxs_status pxs_inertia(pxs_symbolic sym, const double* Hval, const double* Sval,
                        int32_t nshift, const double* eps, void* Lbuf, void* work,
                        int64_t* neg_count, int64_t* info, void* stream);
 
+/* Inertia counts (Sec. II.C) enqueued on `stream` without waiting for the
+ * device, for callers that overlap counts with other work (a serving
+ * loop): eps (device, nshift doubles) holds the real shifts; after the
+ * stream reaches this point neg_count (device, nshift int64) holds
+ * #{k : d_k < 0} of H - eps[q] S and info (device, nshift int64) the
+ * 1-based column of a tiny pivot or 0 (a flagged count is unreliable: shift
+ * eps slightly and count again).  Every launch runs on `stream` (no library
+ * streams).  Lbuf and work as for pxs_inertia; the arrays must stay valid
+ * until the stream has passed this call. */
+pxs_status pxs_inertia_async(pxs_symbolic sym, const double* Hval, const double* Sval,
+                             int32_t nshift, const double* eps, void* Lbuf, void* work,
+                             int64_t* neg_count, int64_t* info, void* stream);
+
 /* Inertia counts of a complex Hermitian pencil (Sec. II.C for Hermitian H,
  * S): the L D U factorization of H - eps[q] S (a Hermitian matrix at a real
  * shift, so D is real up to rounding) and neg_count[q] = #{k : Re d_k < 0}
@@ -315,7 +328,53 @@ pxs_status pxs_plan_run(pxs_plan plan, const pxs_c64* shifts, const pxs_c64* wei
  * the last run of the plan, after synchronising `stream` (the stream the run
  * was enqueued on, or one ordered after it). */
 pxs_status pxs_plan_results(pxs_plan plan, double* traces, int64_t* info, void* stream);
+/* pxs_plan_run with the pole table already on the device: shifts (device,
+ * nshift) and weights (device, nsets * nshift, set-major) are copied into
+ * the workspace on `stream` and the graph replayed there; nothing waits for
+ * the device (the shifts are not checked for finiteness).  With
+ * pxs_plan_copy_results a caller can queue several runs of one plan (pole
+ * chunks of one request, PXS_PLAN_ACCUMULATE) back to back. */
+pxs_status pxs_plan_run_device(pxs_plan plan, const pxs_c64* shifts, const pxs_c64* weights,
+                               void* stream);
+/* Enqueues copies of the last run's traces (device, 2 * nsets doubles,
+ * nullable) and tiny-pivot info (device, nshift int64, nullable) on
+ * `stream`, without waiting: a later run of the same plan overwrites the
+ * workspace values, the copies do not change. */
+pxs_status pxs_plan_copy_results(pxs_plan plan, double* traces, int64_t* info, void* stream);
 void pxs_plan_free(pxs_plan plan);
+
+/* ---------------------------------------------------------------------- */
+/* Fused batch of systems (Sec. II.B: the poles of one system and separate
+ * systems are independent, so their panel operations can share launches).
+ * The density matrices of nsys real symmetric systems, each with its own
+ * bound symbolic handle (no SelInv shift chunk), values, nshift[i] shifts
+ * and caller buffers as for pxs_plan_create (Lbuf[i], work[i], out[i]:
+ * device nsets * nnz_lower doubles), run as one sequence of launches: each
+ * launch takes the next panel operation of every system whose next
+ * operation uses the same kernel, as one grid.  Every system's operations
+ * keep the order of its single-stream run, so its factors, selected
+ * inverses and pole sums are the same bits as an eager run of it alone.
+ * pxs_batch_create plans the launches (host only); pxs_batch_info reports
+ * the device bytes of the launch table (table_bytes) and the number of
+ * fused launches; pxs_batch_bind copies the table into `table` (device,
+ * 256-byte aligned, kept until pxs_batch_free) and captures the whole
+ * sequence (assembly, factorizations, selected inversions, pole sums) as
+ * one HIP graph on a private stream.  pxs_batch_run uploads the pole tables
+ * (host: shifts concatenated over the systems, sum nshift; weights
+ * concatenated over the systems, each nsets * nshift[i] set-major) on
+ * `stream` and replays the graph there; pxs_batch_results synchronises
+ * `stream` and returns traces (host, nsys * 2 * nsets, nullable: system i's
+ * Tr(G^g S), Tr(G^g H) at 2 * nsets * i + 2g) and info (host, sum nshift,
+ * nullable).  Calls on one batch must not overlap (shared buffers). */
+typedef struct pxs_batch_s* pxs_batch;
+pxs_status pxs_batch_create(int32_t nsys, const pxs_symbolic* syms, const double* const* Hval,
+                            const double* const* Sval, const int32_t* nshift, int32_t nsets,
+                            void* const* Lbuf, void* const* work, double* const* out, pxs_batch* batch);
+pxs_status pxs_batch_info(pxs_batch batch, int64_t* table_bytes, int64_t* launches);
+pxs_status pxs_batch_bind(pxs_batch batch, void* table, void* stream);
+pxs_status pxs_batch_run(pxs_batch batch, const pxs_c64* shifts, const pxs_c64* weights, void* stream);
+pxs_status pxs_batch_results(pxs_batch batch, double* traces, int64_t* info, void* stream);
+void pxs_batch_free(pxs_batch batch);
 
 /* Kernel timing for benchmarks: while a profile is open, every launch of the
  * selected kernel class is bracketed by HIP events on its launch stream.

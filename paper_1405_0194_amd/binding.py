@@ -78,6 +78,15 @@ def load():
         "pxs_get_diag": (C.c_int, [_P, C.c_int32, _P, _P]),
         "pxs_inertia": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
         "pxs_inertia_hermitian": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+        "pxs_inertia_async": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P, _P, _P, _P]),
+        "pxs_plan_run_device": (C.c_int, [_P, _P, _P, _P]),
+        "pxs_plan_copy_results": (C.c_int, [_P, _P, _P, _P]),
+        "pxs_batch_create": (C.c_int, [C.c_int32, _P, _P, _P, _P, C.c_int32, _P, _P, _P, _P]),
+        "pxs_batch_info": (C.c_int, [_P, _P, _P]),
+        "pxs_batch_bind": (C.c_int, [_P, _P, _P]),
+        "pxs_batch_run": (C.c_int, [_P, _P, _P, _P]),
+        "pxs_batch_results": (C.c_int, [_P, _P, _P, _P]),
+        "pxs_batch_free": (None, [_P]),
         "pxs_density_matrix": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
                                          C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
         "pxs_density_matrix_noalloc": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_double, C.c_int32,
@@ -137,6 +146,13 @@ def _require(t, nbytes, what):
         raise ValueError(f"{what}: {_nbytes(t)} bytes, needs {nbytes}")
     if t.data_ptr() % 256:
         raise ValueError(f"{what}: must be 256-byte aligned")
+
+
+def _require_vec(t, dtype, n, what):
+    """A small device array passed as a raw pointer: contiguous, right type
+    and at least n elements."""
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype or t.numel() < n:
+        raise ValueError(f"{what}: needs a contiguous {dtype} device tensor of {n} elements")
 
 
 def _require_values(analysis, H, S):
@@ -456,6 +472,25 @@ class Plan:
         nnz = self.analysis.info["nnz_lower"]
         return self.out.view(self.nsets, nnz), (tr.reshape(self.nsets, 2) if sync else None), info
 
+    def run_device(self, shifts, weights, stream=None):
+        """Replays the graph with a pole table already on the device
+        (complex128 tensors: shifts (nshift,), weights (nsets * nshift,)
+        set-major); waits for nothing."""
+        import torch
+        _require_vec(shifts, torch.complex128, self.nshift, "shifts")
+        _require_vec(weights, torch.complex128, self.nsets * self.nshift, "weights")
+        _check("pxs_plan_run_device", self._lib.pxs_plan_run_device(self._h, _dptr(shifts), _dptr(weights),
+                                                                     _stream(stream)))
+
+    def copy_results(self, traces, info, stream=None):
+        """Enqueues copies of the last run's traces (float64 device tensor of
+        2 * nsets) and pivot info (int64 device tensor of nshift)."""
+        import torch
+        _require_vec(traces, torch.float64, 2 * self.nsets, "traces")
+        _require_vec(info, torch.int64, self.nshift, "info")
+        _check("pxs_plan_copy_results", self._lib.pxs_plan_copy_results(self._h, _dptr(traces), _dptr(info),
+                                                                         _stream(stream)))
+
     def results(self, stream=None):
         """(traces (nsets, 2), info) of the last run (synchronises stream)."""
         tr = np.zeros(2 * self.nsets)
@@ -491,6 +526,23 @@ def inertia(analysis: Analysis, H, S, eps, L=None, work=None, stream=None):
                            _ptr(neg), _ptr(info), _stream(stream))
     _check("pxs_inertia", code, allow=(PXS_OK, PXS_TINY_PIVOT))
     return neg, info
+
+
+def inertia_async(analysis: Analysis, H, S, eps, neg, info, L, work, stream=None):
+    """Enqueues the inertia counts of H - eps_q S (eps: float64 device
+    tensor) into the int64 device tensors neg and info on `stream`, without
+    waiting for the device."""
+    import torch
+    lib = load()
+    q = eps.numel()
+    _require_vec(eps, torch.float64, q, "eps")
+    _require_vec(neg, torch.int64, q, "neg")
+    _require_vec(info, torch.int64, q, "info")
+    _require_values(analysis, H, S)
+    _require(L, q * analysis.info["bytes_per_shift"] // 2, "factor storage")
+    _require(work, analysis.workspace_size(q, real=True), "workspace")
+    _check("pxs_inertia_async", lib.pxs_inertia_async(analysis._h, _dptr(H), _dptr(S), q, _dptr(eps), _dptr(L),
+                                                       _dptr(work), _dptr(neg), _dptr(info), _stream(stream)))
 
 
 def inertia_hermitian(analysis: Analysis, H, S, eps, L=None, work=None, stream=None):
@@ -543,6 +595,79 @@ def density_matrix(analysis: Analysis, H, S, beta, dE, mu, P, nsets=2, L=None, w
                                   _stream(stream))
     _check("pxs_density_matrix", code, allow=(PXS_OK, PXS_TINY_PIVOT))
     return out.view(nsets, nnz), tr.reshape(nsets, 2), info, sh, wt.reshape(nsets, P)
+
+
+class FusedBatch:
+    """The density matrices of several real systems as one sequence of
+    fused launches captured in one HIP graph (pxs_batch_*).  systems: list
+    of (analysis, H, S, nshift); buffers: optional list of (L, work) device
+    tensors per system (views into a shared arena, say), else allocated
+    here; the outputs and the launch table are allocated here."""
+
+    def __init__(self, systems, nsets=2, device="cuda", buffers=None):
+        import torch
+        lib = load()
+        self._lib = lib
+        self.nsets = int(nsets)
+        self.systems = []
+        for i, (a, H, S, P) in enumerate(systems):
+            a.bind(device)
+            _require_values(a, H, S)
+            L, W = buffers[i] if buffers is not None else a.buffers(P, device=device)
+            _require(L, int(P) * a.info["bytes_per_shift"], "factor storage")
+            _require(W, a.workspace_size(int(P)), "workspace")
+            out = torch.empty(self.nsets * a.info["nnz_lower"], dtype=torch.float64, device=device)
+            self.systems.append((a, H, S, int(P), L, W, out))
+        n = len(self.systems)
+        arr = lambda vals: (_P * n)(*vals)
+        self.nshift = np.array([y[3] for y in self.systems], dtype=np.int32)
+        h = _P()
+        _check("pxs_batch_create", lib.pxs_batch_create(
+            n, arr([y[0]._h for y in self.systems]), arr([_dptr(y[1]) for y in self.systems]),
+            arr([_dptr(y[2]) for y in self.systems]), _ptr(self.nshift), self.nsets,
+            arr([_dptr(y[4]) for y in self.systems]), arr([_dptr(y[5]) for y in self.systems]),
+            arr([_dptr(y[6]) for y in self.systems]), C.byref(h)))
+        self._h = h
+        tb, nl = C.c_int64(), C.c_int64()
+        _check("pxs_batch_info", lib.pxs_batch_info(h, C.byref(tb), C.byref(nl)))
+        self.launches = nl.value
+        self.table = torch.empty(max(256, tb.value), dtype=torch.uint8, device=device)
+        _check("pxs_batch_bind", lib.pxs_batch_bind(h, _dptr(self.table), _stream()))
+
+    def footprint(self):
+        """Device bytes of the buffers this batch allocated itself."""
+        return sum(_nbytes(y[6]) for y in self.systems) + _nbytes(self.table)
+
+    def run(self, tables, stream=None):
+        """tables: per system (shifts (nshift,), weights (nsets, nshift)).
+        Uploads them and replays the graph on `stream` (no wait)."""
+        sh = np.concatenate([np.ascontiguousarray(t[0], dtype=np.complex128) for t in tables])
+        wt = np.concatenate([np.ascontiguousarray(t[1], dtype=np.complex128).reshape(-1) for t in tables])
+        _check("pxs_batch_run", self._lib.pxs_batch_run(self._h, _ptr(sh), _ptr(wt), _stream(stream)))
+
+    def results(self, stream=None):
+        """(list of traces (nsets, 2) per system, list of info per system)
+        after synchronising `stream`."""
+        n = len(self.systems)
+        tr = np.zeros(2 * self.nsets * n)
+        info = np.zeros(int(self.nshift.sum()), dtype=np.int64)
+        _check("pxs_batch_results", self._lib.pxs_batch_results(self._h, _ptr(tr), _ptr(info), _stream(stream)),
+               allow=(PXS_OK, PXS_TINY_PIVOT))
+        tr = tr.reshape(n, self.nsets, 2)
+        offs = np.concatenate([[0], np.cumsum(self.nshift)])
+        return [tr[i] for i in range(n)], [info[offs[i]:offs[i + 1]] for i in range(n)]
+
+    def outputs(self):
+        """Per system the (nsets, nnz) pole-sum output tensor."""
+        return [y[6].view(self.nsets, -1) for y in self.systems]
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                self._lib.pxs_batch_free(self._h)
+                self._h = None
+        except Exception:
+            pass
 
 
 def density_matrix_noalloc(analysis: Analysis, H, S, beta, dE, mu, P, nsets=2, L=None, out=None,

@@ -389,6 +389,18 @@ pxs_status pxs_inertia(pxs_symbolic sym, const double* Hval, const double* Sval,
   return tiny ? PXS_TINY_PIVOT : PXS_OK;
 }
 
+pxs_status pxs_inertia_async(pxs_symbolic sym, const double* Hval, const double* Sval, int32_t nshift,
+                             const double* eps, void* Lbuf, void* work, int64_t* neg_count, int64_t* info,
+                             void* stream) {
+  pxs_status s0 = check_numeric_args(sym, Hval, Sval, nshift, Lbuf, work);
+  if (s0 != PXS_OK) return s0;
+  if (!eps || !neg_count || !info) return PXS_EINVAL;
+  const int e = pxs::run_inertia_async(sym->S, Hval, Sval, nshift, eps, Lbuf, work, neg_count, info,
+                                       (hipStream_t)stream);
+  if (e != 0) return hip_fail(e);
+  return PXS_OK;
+}
+
 pxs_status pxs_inertia_hermitian(pxs_symbolic sym, const pxs_c64* Hval, const pxs_c64* Sval, int32_t nshift,
                                  const double* eps, void* Lbuf, void* work, int64_t* neg_count, int64_t* info,
                                  void* stream) {
@@ -571,6 +583,30 @@ pxs_status pxs_plan_run(pxs_plan plan, const pxs_c64* shifts, const pxs_c64* wei
   return PXS_OK;
 }
 
+pxs_status pxs_plan_run_device(pxs_plan plan, const pxs_c64* shifts, const pxs_c64* weights, void* stream) {
+  if (!plan || !shifts || !weights) return PXS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  int k = pxs::upload_shifts_device(plan->nshift, (const double*)shifts, plan->work, st);
+  if (k == 0) k = pxs::upload_weights_device(plan->nshift, plan->nsets, (const double*)weights, plan->work, st);
+  if (k == 0) k = (int)hipGraphLaunch(plan->exec, st);
+  if (k != 0) return hip_fail(k);
+  return PXS_OK;
+}
+
+pxs_status pxs_plan_copy_results(pxs_plan plan, double* traces, int64_t* info, void* stream) {
+  if (!plan) return PXS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t he = hipSuccess;
+  if (traces)
+    he = hipMemcpyAsync(traces, (char*)plan->work + pxs::WK_TRACES, sizeof(double) * 2 * plan->nsets,
+                        hipMemcpyDeviceToDevice, st);
+  if (he == hipSuccess && info)
+    he = hipMemcpyAsync(info, (char*)plan->work + pxs::WK_INFO, sizeof(int64_t) * plan->nshift,
+                        hipMemcpyDeviceToDevice, st);
+  if (he != hipSuccess) return hip_fail(he);
+  return PXS_OK;
+}
+
 pxs_status pxs_plan_results(pxs_plan plan, double* traces, int64_t* info, void* stream) {
   if (!plan) return PXS_EINVAL;
   hipStream_t st = (hipStream_t)stream;
@@ -598,6 +634,147 @@ void pxs_plan_free(pxs_plan plan) {
   if (plan->graph) (void)hipGraphDestroy(plan->graph);
   for (hipEvent_t e : plan->events) hipEventDestroy(e);
   delete plan;
+}
+
+struct pxs_batch_s {
+  pxs::BatchPlan* plan = nullptr;
+  std::vector<pxs::BatchSys> sys;
+  int32_t nsets = 0;
+  int64_t total_shifts = 0;
+  bool bound = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<double> shifts, weights;   // host staging (sources of the uploads)
+};
+
+pxs_status pxs_batch_create(int32_t nsys, const pxs_symbolic* syms, const double* const* Hval,
+                            const double* const* Sval, const int32_t* nshift, int32_t nsets, void* const* Lbuf,
+                            void* const* work, double* const* out, pxs_batch* batch) {
+  if (!batch || nsys < 1 || !syms || !Hval || !Sval || !nshift || !Lbuf || !work || !out) return PXS_EINVAL;
+  if (nsets < 1 || nsets > 4) return PXS_EINVAL;
+  *batch = nullptr;
+  std::vector<pxs::BatchSys> sys;
+  int64_t total = 0;
+  try {
+    for (int32_t i = 0; i < nsys; ++i) {
+      pxs_status s0 = check_numeric_args(syms[i], Hval[i], Sval[i], nshift[i], Lbuf[i], work[i]);
+      if (s0 != PXS_OK) return s0;
+      const pxs::Symbolic& S = syms[i]->S;
+      // the fused path runs SelInv on all shifts at once, on one stream
+      if (S.selinv_chunk > 0 && S.selinv_chunk < nshift[i]) {
+        g_last_error = "pxs_batch_create: system " + std::to_string(i) + " has a SelInv shift chunk";
+        return PXS_EINVAL;
+      }
+      if (!out[i]) return PXS_EINVAL;
+      sys.push_back(pxs::BatchSys{&S, Hval[i], Sval[i], nshift[i], Lbuf[i], work[i], out[i]});
+      total += nshift[i];
+    }
+  } catch (const std::bad_alloc&) {
+    return PXS_ENOMEM;
+  }
+  pxs_batch_s* b = new (std::nothrow) pxs_batch_s;
+  if (!b) return PXS_ENOMEM;
+  int err = 0;
+  b->plan = pxs::batch_create(sys, nsets, &err);
+  if (!b->plan) {
+    delete b;
+    return err == (int)hipErrorOutOfMemory ? PXS_ENOMEM : hip_fail(err);
+  }
+  b->sys = sys;
+  b->nsets = nsets;
+  b->total_shifts = total;
+  *batch = b;
+  return PXS_OK;
+}
+
+pxs_status pxs_batch_info(pxs_batch batch, int64_t* table_bytes, int64_t* launches) {
+  if (!batch) return PXS_EINVAL;
+  if (table_bytes) *table_bytes = pxs::batch_table_bytes(batch->plan);
+  if (launches) *launches = pxs::batch_launches(batch->plan);
+  return PXS_OK;
+}
+
+pxs_status pxs_batch_bind(pxs_batch batch, void* table, void* stream) {
+  if (!batch || batch->bound) return batch ? PXS_ESTATE : PXS_EINVAL;
+  if (!table || !aligned256(table)) return PXS_EINVAL;
+  int k = pxs::batch_bind(batch->plan, table, (hipStream_t)stream);
+  hipStream_t cs = nullptr;
+  if (k == 0) k = (int)hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (k == 0) {
+    k = (int)hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (k == 0) {
+      k = pxs::run_batch_kernels(batch->plan, cs);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(cs, &g);
+      if (e2 == hipSuccess) batch->graph = g;
+      if (k == 0 && e2 != hipSuccess) k = (int)e2;
+    }
+  }
+  if (k == 0) k = (int)hipGraphInstantiate(&batch->exec, batch->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (k != 0) return hip_fail(k);
+  batch->bound = true;
+  return PXS_OK;
+}
+
+pxs_status pxs_batch_run(pxs_batch batch, const pxs_c64* shifts, const pxs_c64* weights, void* stream) {
+  if (!batch || !shifts || !weights) return PXS_EINVAL;
+  if (!batch->bound) return PXS_ESTATE;
+  for (int64_t l = 0; l < batch->total_shifts; ++l)
+    if (!std::isfinite(shifts[l].re) || !std::isfinite(shifts[l].im)) return PXS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  batch->shifts.assign((const double*)shifts, (const double*)shifts + 2 * batch->total_shifts);
+  batch->weights.assign((const double*)weights, (const double*)weights + 2 * batch->nsets * batch->total_shifts);
+  int k = 0;
+  int64_t o = 0;
+  for (const pxs::BatchSys& y : batch->sys) {
+    k = pxs::upload_shifts(y.nshift, batch->shifts.data() + 2 * o, y.work, st);
+    if (k == 0) k = pxs::upload_weights(y.nshift, batch->nsets, batch->weights.data() + 2 * batch->nsets * o,
+                                        y.work, st);
+    if (k != 0) return hip_fail(k);
+    o += y.nshift;
+  }
+  k = (int)hipGraphLaunch(batch->exec, st);
+  if (k != 0) return hip_fail(k);
+  return PXS_OK;
+}
+
+pxs_status pxs_batch_results(pxs_batch batch, double* traces, int64_t* info, void* stream) {
+  if (!batch) return PXS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nb = batch->sys.size();
+  std::vector<double> t8(8 * nb);
+  std::vector<int64_t> inf(batch->total_shifts);
+  hipError_t he = hipSuccess;
+  int64_t o = 0;
+  for (size_t i = 0; i < nb && he == hipSuccess; ++i) {
+    const pxs::BatchSys& y = batch->sys[i];
+    he = hipMemcpyAsync(t8.data() + 8 * i, (char*)y.work + pxs::WK_TRACES, 8 * sizeof(double),
+                        hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(inf.data() + o, (char*)y.work + pxs::WK_INFO, sizeof(int64_t) * y.nshift,
+                          hipMemcpyDeviceToHost, st);
+    o += y.nshift;
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) return hip_fail(he);
+  if (traces)
+    for (size_t i = 0; i < nb; ++i)
+      for (int g = 0; g < 2 * batch->nsets; ++g) traces[2 * batch->nsets * i + g] = t8[8 * i + g];
+  bool tiny = false;
+  for (int64_t l = 0; l < batch->total_shifts; ++l) {
+    if (info) info[l] = inf[l];
+    tiny = tiny || inf[l] != 0;
+  }
+  return tiny ? PXS_TINY_PIVOT : PXS_OK;
+}
+
+void pxs_batch_free(pxs_batch batch) {
+  if (!batch) return;
+  if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+  if (batch->graph) (void)hipGraphDestroy(batch->graph);
+  pxs::batch_destroy(batch->plan);
+  delete batch;
 }
 
 pxs_status pxs_profile_begin(int32_t kernel) {

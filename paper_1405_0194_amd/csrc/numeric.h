@@ -42,6 +42,14 @@ int run_pole_sum_kernels(const Symbolic& S, int nshift, const void* L, void* wor
                          const double* Sv, int nsets, double* out, int accumulate, hipStream_t st);
 int upload_shifts(int nshift, const double* shifts_host, void* work, hipStream_t st);
 int upload_weights(int nshift, int nsets, const double* weights_host, void* work, hipStream_t st);
+// the same from device arrays (stream-ordered, no host involvement)
+int upload_shifts_device(int nshift, const double* shifts_dev, void* work, hipStream_t st);
+int upload_weights_device(int nshift, int nsets, const double* weights_dev, void* work, hipStream_t st);
+// Inertia counts enqueued without host synchronisation: real shifts from a
+// device array, the real LDL^T on the caller's stream, the negative-pivot
+// counts and tiny-pivot columns copied to device arrays.
+int run_inertia_async(const Symbolic& S, const double* H, const double* Sv, int nshift, const double* eps_dev,
+                      void* L, void* work, int64_t* neg_dev, int64_t* info_dev, hipStream_t st);
 // events: nullptr (library pool) or selinv_event_count(S) events owned by
 // the caller (a graph plan).
 int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st,
@@ -65,6 +73,29 @@ int run_pole_sum(const Symbolic& S, int nshift, const void* L, void* work, const
                  hipStream_t st);
 int run_gather(const Symbolic& S, int shift, const void* L, void* out, hipStream_t st);
 int run_get_diag(const Symbolic& S, int shift, bool cplx, const void* L, void* out, hipStream_t st);
+
+// Fused execution of several systems' density matrices (batch.inc).
+struct BatchSys {
+  const Symbolic* S;
+  const double* H;
+  const double* Sv;
+  int32_t nshift;
+  void* L;
+  void* work;
+  double* out;
+};
+struct BatchPlan;   // the schedule and its item table (host), opaque here
+// Builds the schedule (host only); nullptr and *err set on failure.
+BatchPlan* batch_create(const std::vector<BatchSys>& sys, int nsets, int* err);
+void batch_destroy(BatchPlan* b);
+int64_t batch_table_bytes(const BatchPlan* b);
+int64_t batch_launches(const BatchPlan* b);
+// Copies the item table to `table` (device, batch_table_bytes) on st and
+// keeps the address for the launches.
+int batch_bind(BatchPlan* b, void* table, hipStream_t st);
+// Assembly, the fused factorization and SelInv, the pole sums (kernels
+// only; the shifts and weights are read from each system's workspace).
+int run_batch_kernels(const BatchPlan* b, hipStream_t st);
 
 // Complex Hermitian pencils (hermitian.inc): L region + U^T region per shift.
 int64_t herm_storage_bytes(const Symbolic& S, int nshift);

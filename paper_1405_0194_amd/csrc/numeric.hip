@@ -34,6 +34,7 @@
 #include <type_traits>
 #include <cstdint>
 #include <cstdio>
+#include <new>
 #include <vector>
 
 #include "pxs_internal.h"
@@ -440,6 +441,15 @@ __global__ void k_fill_zero(double2* p, int64_t n2) {
   for (; i < n2; i += stride) p[i] = make_double2(0.0, 0.0);
 }
 
+// Real shifts eps_q as the complex shifts (eps_q, 0) of an inertia batch.
+__global__ void k_real_shifts(const double* __restrict__ eps, double* __restrict__ shifts, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) {
+    shifts[2 * q] = eps[q];
+    shifts[2 * q + 1] = 0.0;
+  }
+}
+
 __global__ void k_zero_i64(int64_t* p, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -536,6 +546,60 @@ __device__ __forceinline__ double* shift_base(const Common& c, int sh) {
   return c.L + (CPLX ? 2 : 1) * c.stride * sh;
 }
 
+// Where a workgroup finds its panel.  OnePanel: one panel of one system per
+// launch (kernel argument), grid = (tiles, shifts).  PanelGroup: a table of
+// panels of several systems launched as one grid of sum(tiles x shifts)
+// workgroups (the fused execution of a batch of systems); each item's
+// workgroups are a contiguous range of logical ids, so after the XCD-aware
+// remap the tiles of one item share an XCD as in a single launch.
+struct OnePanel {
+  Common c;
+  PanelK p;
+};
+
+struct GroupItem {
+  Common c;
+  PanelK p;
+  int64_t start;   // first logical workgroup of the item
+  int32_t tiles;   // workgroups per shift
+  int32_t nsh;     // shifts
+};
+
+struct PanelGroup {
+  const GroupItem* items;
+  int32_t n;
+};
+
+// remap: XCD-aware order (else the plain one); bx = tile, by = shift
+__device__ __forceinline__ void locate(const OnePanel& src, Common& c, PanelK& p, int& bx, int& by, bool remap) {
+  c = src.c;
+  p = src.p;
+  if (remap) {
+    xcd_remap(bx, by);
+  } else {
+    bx = blockIdx.x;
+    by = blockIdx.y;
+  }
+}
+
+__device__ __forceinline__ void locate(const PanelGroup& src, Common& c, PanelK& p, int& bx, int& by, bool remap) {
+  int lx = (int)blockIdx.x, ly = 0;
+  if (remap) xcd_remap(lx, ly);   // grid (total, 1): ly stays 0
+  const int64_t lid = lx;
+  int lo = 0, hi = src.n - 1;     // the last item starting at or before lid
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (src.items[mid].start <= lid) lo = mid;
+    else hi = mid - 1;
+  }
+  const GroupItem& it = src.items[lo];
+  c = it.c;
+  p = it.p;
+  const int64_t local = lid - it.start;
+  bx = (int)(local % it.tiles);
+  by = (int)(local / it.tiles);
+}
+
 // Dense LDL^T of the panel's wp x wp diagonal block in LDS, with L_pp^{-1}
 // accumulated along the way.  Step k (one barrier per step, 512 threads, row
 // r = t % 64 and every eighth column per thread):
@@ -549,8 +613,8 @@ __device__ __forceinline__ double* shift_base(const Common& c, int sh) {
 // are formed in the same step (look-ahead) and no second barrier is needed.
 constexpr int NTD = 512;
 
-template <bool CPLX>
-__global__ void __launch_bounds__(NTD) k_diag(Common c, PanelK p) {
+template <bool CPLX, class Src>
+__global__ void __launch_bounds__(NTD) k_diag(Src src) {
   __shared__ double a_re[64][LDP];   // a[col][row]: working matrix, then L^{-1} (strict lower)
   __shared__ double a_im[CPLX ? 64 : 1][LDP];
   __shared__ double l_re[64][LDP];   // l[col][row]: L (strict lower)
@@ -559,7 +623,10 @@ __global__ void __launch_bounds__(NTD) k_diag(Common c, PanelK p) {
   __shared__ double dd_im[2][CPLX ? 64 : 1];
   __shared__ double pv_re[64];       // pivots d_k
   __shared__ double pv_im[CPLX ? 64 : 1];
-  const int sh = blockIdx.y;
+  Common c;
+  PanelK p;
+  int bx, sh;
+  locate(src, c, p, bx, sh, false);
   double* Ls = shift_base<CPLX>(c, sh);
   const int wp = p.wp;
   const int t = threadIdx.x;
@@ -666,12 +733,14 @@ __global__ void __launch_bounds__(NTD) k_diag(Common c, PanelK p) {
 // workgroup per CU), a 64-row tile 67 KB (two per CU).
 #define PXS_LB(TNv) __launch_bounds__(NT, (TNv) == 64 ? 2 : 1)
 
-template <bool CPLX, int TN>
-__global__ void PXS_LB(TN) k_trsm(Common c, PanelK p) {
+template <bool CPLX, int TN, class Src>
+__global__ void PXS_LB(TN) k_trsm(Src src) {
   __shared__ Stage2<CPLX, TN> s;
   __shared__ cplx dinv[64];
+  Common c;
+  PanelK p;
   int bx, by;
-  xcd_remap(bx, by);
+  locate(src, c, p, bx, by, true);
   const int sh = by;
   double* Ls = shift_base<CPLX>(c, sh);
   const int i0 = bx * TN;
@@ -705,11 +774,13 @@ __global__ void PXS_LB(TN) k_trsm(Common c, PanelK p) {
 // Left-looking update of panel p from the earlier columns of its own
 // supernode: A[r][c] -= sum_{k < p0} L[r][k] d_k L[c][k] for rows r >= p0 of
 // the row list and the panel's columns c.  P[c][r] = sum_k (d_k L[c][k]) L[r][k].
-template <bool CPLX, int TN>
-__global__ void PXS_LB(TN) k_int_update(Common c, PanelK p) {
+template <bool CPLX, int TN, class Src>
+__global__ void PXS_LB(TN) k_int_update(Src src) {
   __shared__ Stage2<CPLX, TN> s;
+  Common c;
+  PanelK p;
   int bx, by;
-  xcd_remap(bx, by);
+  locate(src, c, p, bx, by, true);
   const int sh = by;
   double* Ls = shift_base<CPLX>(c, sh);
   const int r0 = bx * TN;            // rows p0 + r0 .. of the row list
@@ -755,11 +826,13 @@ __device__ __forceinline__ void tri_index(int b, int& ti, int& tj) {
 // maps (B = row-list positions from p0 + wp on).  Used once per supernode
 // with K = all of its columns (p0 = 0, wp = w_J, B = the rows below it).
 // P[j][i] = sum_k (d_k L[j][k]) L[i][k].
-template <bool CPLX, int TN>
-__global__ void PXS_LB(TN) k_update(Common c, PanelK p) {
+template <bool CPLX, int TN, class Src>
+__global__ void PXS_LB(TN) k_update(Src src) {
   __shared__ Stage2<CPLX, TN> s;
+  Common c;
+  PanelK p;
   int bx, by;
-  xcd_remap(bx, by);
+  locate(src, c, p, bx, by, true);
   const int sh = by;
   double* Ls = shift_base<CPLX>(c, sh);
   // tiles: 64 columns j (m) by 128 rows i (n); only tiles that reach the
@@ -812,11 +885,13 @@ __device__ __forceinline__ double* wbase(const Common& c, int sh) {
 }
 
 // W = L_Bp Linv: P[c][i] = sum_k Linv[k][c] L[i][k]; W stored W[c * nb + i].
-template <int TN>
-__global__ void PXS_LB(TN) k_lhat(Common c, PanelK p) {
+template <int TN, class Src>
+__global__ void PXS_LB(TN) k_lhat(Src src) {
   __shared__ Stage2<true, TN> s;
+  Common c;
+  PanelK p;
   int bx, by;
-  xcd_remap(bx, by);
+  locate(src, c, p, bx, by, true);
   const int sh = p.sh0 + by;
   double* Ls = shift_base<true>(c, sh);
   double* W = wbase(c, sh);
@@ -848,11 +923,13 @@ __global__ void PXS_LB(TN) k_lhat(Common c, PanelK p) {
 // part inside the supernode's own columns is read from the supernode's
 // storage (column min(i, k), row max(i, k)), the part in the rows below it
 // from the dense copy G of Z_CC made by k_gather_cc.
-template <int TN>
-__global__ void PXS_LB(TN) k_selinv_off(Common c, PanelK p) {
+template <int TN, class Src>
+__global__ void PXS_LB(TN) k_selinv_off(Src src) {
   __shared__ Stage2<true, TN> s;
+  Common c;
+  PanelK p;
   int bx, by;
-  xcd_remap(bx, by);
+  locate(src, c, p, bx, by, true);
   const int sh = p.sh0 + by;
   double* Ls = shift_base<true>(c, sh);
   const double* W = wbase(c, sh);
@@ -890,12 +967,17 @@ __global__ void PXS_LB(TN) k_selinv_off(Common c, PanelK p) {
 // gathered from the ancestors' storage through the maps.  Each thread moves
 // 16 elements of a 64 x 64 tile: first all relative row positions, then all
 // values, then the stores, so the loads of a thread are in flight together.
-__global__ void __launch_bounds__(NT) k_gather_cc(Common c, PanelK p) {
-  const int sh = p.sh0 + blockIdx.y;
+template <class Src>
+__global__ void __launch_bounds__(NT) k_gather_cc(Src src) {
+  Common c;
+  PanelK p;
+  int bx, by;
+  locate(src, c, p, bx, by, false);
+  const int sh = p.sh0 + by;
   const double* Ls = shift_base<true>(c, sh);
-  double* G = c.G + c.gstride * blockIdx.y;
+  double* G = c.G + c.gstride * by;
   int ta, tb;
-  tri_index(blockIdx.x, ta, tb);
+  tri_index(bx, ta, tb);
   const int a0 = ta * TM, b0 = tb * TM;
   const int cc = p.c, w = p.w;
   const int64_t* cmap = c.colmap + p.cm;
@@ -925,10 +1007,13 @@ __global__ void __launch_bounds__(NT) k_gather_cc(Common c, PanelK p) {
 }
 
 // Partial W^T Z_Bp over k in [split * SPLIT_ROWS, ...): P[c][r] = sum_k Z[k][c] W[k][r].
-__global__ void PXS_LB(64) k_selinv_diag_partial(Common c, PanelK p) {
+template <class Src>
+__global__ void PXS_LB(64) k_selinv_diag_partial(Src src) {
   __shared__ Stage2<true, TM> s;
+  Common c;
+  PanelK p;
   int bx, by;
-  xcd_remap(bx, by);
+  locate(src, c, p, bx, by, true);
   const int sh = p.sh0 + by;
   const int sp = bx;
   double* Ls = shift_base<true>(c, sh);
@@ -959,12 +1044,17 @@ __global__ void PXS_LB(64) k_selinv_diag_partial(Common c, PanelK p) {
 // by the same workgroup that writes it) with 1024 threads: a wave holds one
 // column cc and its 64 rows, so the work per wave follows the triangle.
 constexpr int NTF = 1024;
-__global__ void __launch_bounds__(NTF) k_selinv_diag_final(Common c, PanelK p) {
+template <class Src>
+__global__ void __launch_bounds__(NTF) k_selinv_diag_final(Src src) {
   __shared__ double l_re[64][LDP];   // l[col][row] = Linv[row][col]
   __shared__ double l_im[64][LDP];
   __shared__ cplx dinv[64];
   constexpr int NE = 64 * 64 / NTF;
-  const int sh = p.sh0 + blockIdx.y;
+  Common c;
+  PanelK p;
+  int bx, by;
+  locate(src, c, p, bx, by, false);
+  const int sh = p.sh0 + by;
   double* Ls = shift_base<true>(c, sh);
   const double* W = wbase(c, sh);
   const double* part = W + 2 * (int64_t)p.nb * p.wp;
@@ -1241,6 +1331,16 @@ int upload_shifts(int nshift, const double* shifts_host, void* work, hipStream_t
   return (int)e;
 }
 
+int upload_shifts_device(int nshift, const double* shifts_dev, void* work, hipStream_t st) {
+  return (int)hipMemcpyAsync((char*)work + WK_SHIFTS, shifts_dev, sizeof(double) * 2 * nshift,
+                             hipMemcpyDeviceToDevice, st);
+}
+
+int upload_weights_device(int nshift, int nsets, const double* weights_dev, void* work, hipStream_t st) {
+  return (int)hipMemcpyAsync((char*)work + WK_WEIGHTS, weights_dev, sizeof(double) * 2 * nsets * nshift,
+                             hipMemcpyDeviceToDevice, st);
+}
+
 int upload_weights(int nshift, int nsets, const double* weights_host, void* work, hipStream_t st) {
   hipError_t e = hipMemcpyAsync((char*)work + WK_WEIGHTS, weights_host,
                                 sizeof(double) * 2 * nsets * nshift, hipMemcpyHostToDevice, st);
@@ -1289,9 +1389,12 @@ int ensure_pool(int nstreams, int nevents) {
   return 0;
 }
 
+// Before the factorization: pivot flags and counts cleared, max|H|, max|S|
+// for the pivot threshold, the factor storage zeroed and every shift's
+// H - w_l S assembled into it.
 template <bool CPLX>
-int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int nshift, void* L,
-                       void* work, hipStream_t st, bool inorder) {
+int factor_prologue(const Symbolic& S, const double* H, const double* Sv, int nshift, void* L, void* work,
+                    hipStream_t st) {
   char* w = (char*)work;
   hipLaunchKernelGGL(k_zero_i64, dim3((2 * MAX_SHIFTS + NT - 1) / NT), dim3(NT), 0, st,
                      (int64_t*)(w + WK_INFO), 2 * MAX_SHIFTS);
@@ -1318,6 +1421,16 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
                        (double*)L, S.nnzL_store, H, Sv, eoff, S.nnz_lower, (const double*)(w + WK_SHIFTS));
   }
   PXS_CHECK_LAUNCH();
+  return 0;
+}
+
+template <bool CPLX>
+int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int nshift, void* L,
+                       void* work, hipStream_t st, bool inorder) {
+  {
+    const int e = factor_prologue<CPLX>(S, H, Sv, nshift, L, work, st);
+    if (e) return e;
+  }
   Common c = make_common(S, L, work);
   const int TR = S.tile_rows;
   const double fm = CPLX ? 8.0 : 2.0;   // flops per multiply-add
@@ -1332,23 +1445,23 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
       ProfScope ps(KC_UPDATE, s, fm * nshift * xm.intu, eb * nshift * ((double)nrows * k.p0 + 2.0 * nrows * k.wp),
                    fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0);
       if (TR == 64)
-        hipLaunchKernelGGL((k_int_update<CPLX, 64>), dim3((nrows + 63) / 64, nshift), dim3(NT), 0, s, c, k);
+        hipLaunchKernelGGL((k_int_update<CPLX, 64, OnePanel>), dim3((nrows + 63) / 64, nshift), dim3(NT), 0, s, OnePanel{c, k});
       else
-        hipLaunchKernelGGL((k_int_update<CPLX, 128>), dim3((nrows + 127) / 128, nshift), dim3(NT), 0, s, c, k);
+        hipLaunchKernelGGL((k_int_update<CPLX, 128, OnePanel>), dim3((nrows + 127) / 128, nshift), dim3(NT), 0, s, OnePanel{c, k});
     }
     {
       ProfScope ps(KC_DIAG, s, fm * nshift * xm.diag, eb * nshift * (double)k.wp * (k.wp + 1),
                    fm * nshift * (double)k.wp * k.wp * k.wp / 3.0);
-      hipLaunchKernelGGL(k_diag<CPLX>, dim3(1, nshift), dim3(NTD), 0, s, c, k);
+      hipLaunchKernelGGL((k_diag<CPLX, OnePanel>), dim3(1, nshift), dim3(NTD), 0, s, OnePanel{c, k});
     }
     if (k.nb > 0) {
       const int nt = (k.nb + TR - 1) / TR;
       ProfScope ps(KC_TRSM, s, fm * nshift * xm.trsm, eb * nshift * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)),
                    fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
       if (TR == 64)
-        hipLaunchKernelGGL((k_trsm<CPLX, 64>), dim3(nt, nshift), dim3(NT), 0, s, c, k);
+        hipLaunchKernelGGL((k_trsm<CPLX, 64, OnePanel>), dim3(nt, nshift), dim3(NT), 0, s, OnePanel{c, k});
       else
-        hipLaunchKernelGGL((k_trsm<CPLX, 128>), dim3(nt, nshift), dim3(NT), 0, s, c, k);
+        hipLaunchKernelGGL((k_trsm<CPLX, 128, OnePanel>), dim3(nt, nshift), dim3(NT), 0, s, OnePanel{c, k});
     }
     PXS_CHECK_LAUNCH();
     return 0;
@@ -1368,9 +1481,9 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
                  eb * nshift * ((double)below * w + (double)below * (below + 1)),
                  fm * nshift * (double)below * (below + 1) / 2.0 * w);
     if (TR == 64)
-      hipLaunchKernelGGL((k_update<CPLX, 64>), dim3(ntj * nti, nshift), dim3(NT), 0, s, c, u);
+      hipLaunchKernelGGL((k_update<CPLX, 64, OnePanel>), dim3(ntj * nti, nshift), dim3(NT), 0, s, OnePanel{c, u});
     else
-      hipLaunchKernelGGL((k_update<CPLX, 128>), dim3(ntj * nti, nshift), dim3(NT), 0, s, c, u);
+      hipLaunchKernelGGL((k_update<CPLX, 128, OnePanel>), dim3(ntj * nti, nshift), dim3(NT), 0, s, OnePanel{c, u});
     PXS_CHECK_LAUNCH();
     return 0;
   };
@@ -1556,7 +1669,7 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
         // bytes: the lower triangle of Z_CC read from the ancestors and written to G, relative positions
         const double gb = (32.0 * nsh + 4.0) * 0.5 * g.c * (g.c + 1);
         ProfScope ps(KC_GATHER, sj, gb, gb, gb);
-        hipLaunchKernelGGL(k_gather_cc, dim3(nt * (nt + 1) / 2, nsh), dim3(NT), 0, sj, c, g);
+        hipLaunchKernelGGL(k_gather_cc<OnePanel>, dim3(nt * (nt + 1) / 2, nsh), dim3(NT), 0, sj, OnePanel{c, g});
       }
       for (int ip = last; ip >= first; --ip) {
         PanelK k = panel_args(S, S.panels[ip]);
@@ -1569,9 +1682,9 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
             ProfScope ps(KC_LHAT, sj, 0.0, 16.0 * nsh * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)),
                          8.0 * nsh * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
             if (TR == 64)
-              hipLaunchKernelGGL(k_lhat<64>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
+              hipLaunchKernelGGL((k_lhat<64, OnePanel>), dim3(nt, nsh), dim3(NT), 0, sj, OnePanel{c, k});
             else
-              hipLaunchKernelGGL(k_lhat<128>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
+              hipLaunchKernelGGL((k_lhat<128, OnePanel>), dim3(nt, nsh), dim3(NT), 0, sj, OnePanel{c, k});
           }
           {
             // bytes: Z_BB (one triangle), L-hat read, Z_Bp written
@@ -1579,18 +1692,18 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
                          16.0 * nsh * (0.5 * k.nb * (k.nb + 1) + 2.0 * k.nb * k.wp),
                          8.0 * nsh * (double)k.nb * k.nb * k.wp);
             if (TR == 64)
-              hipLaunchKernelGGL(k_selinv_off<64>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
+              hipLaunchKernelGGL((k_selinv_off<64, OnePanel>), dim3(nt, nsh), dim3(NT), 0, sj, OnePanel{c, k});
             else
-              hipLaunchKernelGGL(k_selinv_off<128>, dim3(nt, nsh), dim3(NT), 0, sj, c, k);
+              hipLaunchKernelGGL((k_selinv_off<128, OnePanel>), dim3(nt, nsh), dim3(NT), 0, sj, OnePanel{c, k});
           }
           {
             ProfScope ps(KC_SELINV_DIAG, sj, 8.0 * nsh * xm.sdiag,
                          16.0 * nsh * (2.0 * k.nb * k.wp + (double)k.wp * k.wp),
                          8.0 * nsh * (double)k.nb * k.wp * k.wp);
-            hipLaunchKernelGGL(k_selinv_diag_partial, dim3(k.split, nsh), dim3(NT), 0, sj, c, k);
+            hipLaunchKernelGGL(k_selinv_diag_partial<OnePanel>, dim3(k.split, nsh), dim3(NT), 0, sj, OnePanel{c, k});
           }
         }
-        hipLaunchKernelGGL(k_selinv_diag_final, dim3(1, nsh), dim3(NTF), 0, sj, c, k);
+        hipLaunchKernelGGL(k_selinv_diag_final<OnePanel>, dim3(1, nsh), dim3(NTF), 0, sj, OnePanel{c, k});
         PXS_CHECK_LAUNCH();
       }
       if (!single && S.cross_child[J]) PXS_HIP(hipEventRecord(ev[J], sj));
@@ -1602,6 +1715,19 @@ int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t s
       }
     }
   }
+  return 0;
+}
+
+int run_inertia_async(const Symbolic& S, const double* H, const double* Sv, int nshift, const double* eps_dev,
+                      void* L, void* work, int64_t* neg_dev, int64_t* info_dev, hipStream_t st) {
+  char* w = (char*)work;
+  hipLaunchKernelGGL(k_real_shifts, dim3((nshift + NT - 1) / NT), dim3(NT), 0, st, eps_dev,
+                     (double*)(w + WK_SHIFTS), nshift);
+  PXS_CHECK_LAUNCH();
+  const int e = run_factor_kernels<false>(S, H, Sv, nshift, L, work, st, true);
+  if (e) return e;
+  PXS_HIP(hipMemcpyAsync(neg_dev, w + WK_NEGC, sizeof(int64_t) * nshift, hipMemcpyDeviceToDevice, st));
+  PXS_HIP(hipMemcpyAsync(info_dev, w + WK_INFO, sizeof(int64_t) * nshift, hipMemcpyDeviceToDevice, st));
   return 0;
 }
 
@@ -1650,5 +1776,6 @@ int run_get_diag(const Symbolic& S, int shift, bool cplx, const void* L, void* o
 }
 
 #include "hermitian.inc"
+#include "batch.inc"
 
 }  // namespace pxs
