@@ -85,19 +85,28 @@ def measured_traffic(kernel, workload):
     return d.get("hbm_bytes_per_launch")
 
 
+def _counter_rows(d):
+    import csv
+    with open(os.path.join(d, "run_counter_collection.csv")) as f:
+        return list(csv.DictReader(f))
+
+
+def _kernel_is(name, kernel):
+    """rocprofv3 kernel names carry the namespace and template arguments."""
+    base = name.split("<")[0].split("(")[0].strip()
+    return base.split("::")[-1] == "k_" + kernel
+
+
 def traffic_from_counters(kernel, workload, fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, commands):
     """Writes the HBM bytes per launch of one kernel from four rocprofv3
     --pmc runs (FETCH_SIZE, WRITE_SIZE of the workload; the same two counters
     over a plain device copy of 1 GiB, which scale the counters to bytes)."""
-    import csv
-
     def values(d, name_pred):
-        with open(os.path.join(d, "run_counter_collection.csv")) as f:
-            return [float(r["Counter_Value"]) for r in csv.DictReader(f) if name_pred(r["Kernel_Name"])]
+        return [float(r["Counter_Value"]) for r in _counter_rows(d) if name_pred(r["Kernel_Name"])]
 
     gib = float(2**30)
     def ours(n):
-        return n.split("<")[0].split("(")[0].strip() == "k_" + kernel
+        return _kernel_is(n, kernel)
 
     fk = values(fetch_dir, ours)
     wk = values(write_dir, ours)
@@ -115,6 +124,41 @@ def traffic_from_counters(kernel, workload, fetch_dir, write_dir, copy_fetch_dir
            "fetch_counter_scale": round(f_scale, 4), "write_counter_scale": round(w_scale, 4),
            "source_hash": kernel_source_hash(), "commands": commands}
     p = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    with open(p, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+    return out
+
+
+def mfma_from_counters(workload, counter_dir, command):
+    """Per kernel, from one rocprofv3 --pmc run of SQ_INSTS_VALU_MFMA_MOPS_F64
+    (FP64 matrix operations / 512), SQ_VALU_MFMA_BUSY_CYCLES, SQ_BUSY_CYCLES
+    and GRBM_GUI_ACTIVE: the FP64 MFMA flops the hardware executed per launch
+    and the fraction of the busy shader cycles in which the matrix cores
+    were busy.  Writes profiles/mfma_<workload>.json."""
+    per = {}
+    for r in _counter_rows(counter_dir):
+        base = r["Kernel_Name"].split("<")[0].split("(")[0].strip().split("::")[-1]
+        if not base.startswith("k_"):
+            continue
+        k = per.setdefault(base, {})
+        k.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    out = {"workload": workload, "command": command, "kernels": {}}
+    for base, c in sorted(per.items()):
+        mops = c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", [])
+        busy = c.get("SQ_VALU_MFMA_BUSY_CYCLES", [])
+        sq = c.get("SQ_BUSY_CYCLES", [])
+        gui = c.get("GRBM_GUI_ACTIVE", [])
+        n = len(mops)
+        if not n:
+            continue
+        e = {"launches": n, "mfma_flops_per_launch": 512.0 * sum(mops) / n}
+        if busy and sq and sum(sq) > 0:
+            e["mfma_busy_per_sq_busy"] = round(sum(busy) / sum(sq), 4)
+        if gui:
+            e["grbm_gui_active_per_launch"] = sum(gui) / len(gui)
+        out["kernels"][base] = e
+    p = os.path.join(ROOT, "profiles", f"mfma_{workload}.json")
     with open(p, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
@@ -396,26 +440,35 @@ def run_serve(args):
 
     def make():
         return [Request(system=r["system"], mu=r["mu"], poles=40, eps=r["eps"]) for r in raw]
+
+    def rounded(d):
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
     from paper_1405_0194_amd import tune
     srv = Server(budget_bytes=250 * 2**30, nstreams=4, tuned=tune.load_cache() or None)
-    sat = srv.run(make(), realtime=False)         # saturated: everything queued at t = 0
-    print(f"# saturated: {sat}", file=sys.stderr, flush=True)
-    lam = sat["req_per_s"]
+    out = {}
+    lam = args.serve_rate
+    if not lam:
+        sat = srv.run(make(), realtime=False, log=sys.stderr)   # saturated: everything queued at t = 0
+        print(f"# saturated: {sat}", file=sys.stderr, flush=True)
+        lam = sat["req_per_s"]
+        out["saturated"] = rounded(sat)
+    loads = [float(x) for x in args.serve_loads.split(",") if x.strip()]
     runs = {}
-    for f in (0.5, 0.8):
+    for f in loads:
         reqs = make()
         for q, ta in zip(reqs, poisson_arrivals(len(reqs), f * lam, seed=int(f * 10))):
             q.arrival = float(ta)
-        runs[f] = srv.run(reqs, realtime=True)
+        runs[f] = srv.run(reqs, realtime=True, log=sys.stderr)
         print(f"# load {f}: {runs[f]}", file=sys.stderr, flush=True)
-    r8 = runs[0.8]
-    res = dict(value=round(r8["pole_solves_per_s"], 4), ms_per_step=round(1e3 * r8["makespan_s"], 3),
-               latency_s={"p50": round(r8["p50_s"], 4), "p99": round(r8["p99_s"], 4)},
-               saturated={k: (round(v, 4) if isinstance(v, float) else v) for k, v in sat.items()},
-               load_0_5={k: (round(v, 4) if isinstance(v, float) else v) for k, v in runs[0.5].items()},
-               load_0_8={k: (round(v, 4) if isinstance(v, float) else v) for k, v in r8.items()},
+        out[f"load_{f}".replace(".", "_")] = rounded(runs[f])
+    main = runs[loads[-1]] if loads else out["saturated"]
+    res = dict(value=round(main["pole_solves_per_s"], 4), ms_per_step=round(1e3 * main["makespan_s"], 3),
+               latency_s={"p50": round(main["p50_s"], 4), "p99": round(main["p99_s"], 4)},
                config={"workload": MULTI["serve"], "requests": len(raw), "kmax": args.kmax,
-                       "rate_req_per_s_at_0_8": round(0.8 * lam, 4)})
+                       "saturated_req_per_s": round(lam, 4), "loads": loads,
+                       "largest_n": max(r["system"].n for r in raw)},
+               **out)
+    srv.close()
     return res
 
 
@@ -442,6 +495,12 @@ def main():
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/<kernel>_<workload>_traffic.json from four rocprofv3 --pmc "
                          "output folders and exit (no GPU use)")
+    ap.add_argument("--traffic-kernels", default="",
+                    help="with --traffic-from: comma list of kernel classes (default: --profile-kernel)")
+    ap.add_argument("--mfma-from", metavar="DIR",
+                    help="write profiles/mfma_<workload>.json from one rocprofv3 --pmc output folder and exit")
+    ap.add_argument("--only-steps", action="store_true",
+                    help="time the steps and print the line, nothing else (for counter runs)")
     ap.add_argument("--batch-mode", default="plans", choices=("fused", "plans"),
                     help="batch: one graph plan per system, or fused multi-system launches")
     ap.add_argument("--batch-streams", type=int, default=4,
@@ -450,6 +509,10 @@ def main():
                     help="batch, fused: systems with at least this share of a wave's work run alone")
     ap.add_argument("--requests", type=int, default=64, help="serve: number of requests")
     ap.add_argument("--kmax", type=int, default=16, help="serve: largest size class (k * 1000)")
+    ap.add_argument("--serve-loads", default="0.5,0.8",
+                    help="serve: Poisson arrival rates as fractions of the saturated rate (comma list)")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="serve: the saturated request rate (req/s) if known; skips the saturated run")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -459,13 +522,22 @@ def main():
 
     if args.traffic_from:
         f, w, cf, cw = args.traffic_from
-        run = (f"python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --selinv-streams 1 "
+        kernels = [k for k in args.traffic_kernels.split(",") if k] or [args.profile_kernel]
+        regex = "|".join("k_" + k for k in kernels)
+        run = (f"python3 bench.py --steps 1 --warmup 0 --only-steps --selinv-streams 1 "
                f"--workload {args.workload}")
-        cmds = [f"rocprofv3 --pmc {c} --kernel-include-regex {args.profile_kernel} -T -f csv -d <dir> -o run "
+        cmds = [f"rocprofv3 --pmc {c} --kernel-include-regex '{regex}' -T -f csv -d <dir> -o run "
                 f"-- {run}" for c in ("FETCH_SIZE", "WRITE_SIZE")]
         cmds += [f"rocprofv3 --pmc {c} -T -f csv -d <dir> -o run -- python3 bench.py --copy-calibration"
                  for c in ("FETCH_SIZE", "WRITE_SIZE")]
-        traffic_from_counters(args.profile_kernel, args.workload, f, w, cf, cw, cmds)
+        for k in kernels:
+            traffic_from_counters(k, args.workload, f, w, cf, cw, cmds)
+        return
+    if args.mfma_from:
+        cmd = ("rocprofv3 --pmc SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CYCLES "
+               "GRBM_GUI_ACTIVE -T -f csv -d <dir> -o run -- python3 bench.py --steps 1 --warmup 0 "
+               f"--only-steps --selinv-streams 1 --workload {args.workload}")
+        mfma_from_counters(args.workload, args.mfma_from, cmd)
         return
 
     import numpy as np
@@ -568,6 +640,18 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kms, klaunch, kwork, kbytes, kstored = B.profile_end(with_bytes=True, with_stored=True)
+    if args.only_steps:
+        avg_ms = kms / max(klaunch, 1)
+        print(json.dumps({"metric": "pole-solves/sec (LDL^T+SelInv), FP64 MFMA %, p50/p99 request latency",
+                          "value": round(P * args.steps / elapsed, 4), "unit": "pole-solves/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": round(1e3 * elapsed / args.steps, 3), "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+                          "config": {"workload": wl["desc"]},
+                          "roofline": {"kernel": args.profile_kernel, "avg_launch_ms": round(avg_ms, 4),
+                                       "launches": klaunch,
+                                       "flops_per_launch": round(kwork / max(klaunch, 1))}}), flush=True)
+        return
 
     # phase breakdown on one extra (untimed) step
     phases = {}

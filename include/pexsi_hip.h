@@ -155,6 +155,12 @@ pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind,
                        int32_t nblk, const int32_t* blkptr, const double* coords,
                        const pxs_options* opt, pxs_symbolic* out);
 
+/* Sizes and work of an analysis (Sec. II.B steps 1-2: the pattern of L
+ * found by the symbolic factorization sets the storage, the workspace and
+ * the flop counts; Sec. II.A: the cost grows like nnz(L) and the dense
+ * products on the supernodes).  info (host) receives the fields of
+ * pxs_syminfo; the sizes are those every later call of this handle needs.
+ * Errors: PXS_EINVAL for a null argument. */
 pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info);
 
 /* Workspace bytes for a batch of nshift shifts (`real`: an inertia batch,
@@ -217,7 +223,8 @@ pxs_status pxs_selinv(pxs_numeric num, void* stream);
  * out[g * nnz_lower + k] = Im sum_l weights[g * nshift + l] * Z_l[k]
  * (device output, input ordering).  traces (host, 2 * nsets, nullable):
  * traces[2g] = Tr(Gamma^g S), traces[2g+1] = Tr(Gamma^g H) over the full
- * symmetric matrices.  Requires pxs_selinv first.
+ * symmetric matrices (two traces per set: no reserved third slot).
+ * Requires pxs_selinv first.
  * Hermitian handles: Gamma^g = (M - M^H) / 2i with M = sum_l w_{g,l} Z_l
  * (the matrix imaginary part; entrywise Im for real pencils); out then holds
  * nsets * nnz_lower complex values (2 doubles each, Gamma_ij for i >= j) and
@@ -225,7 +232,12 @@ pxs_status pxs_selinv(pxs_numeric num, void* stream);
 pxs_status pxs_pole_sum(pxs_numeric num, int32_t nsets, const pxs_c64* weights,
                         double* out, double* traces, void* stream);
 
-/* Z_l on the input pattern (device out[nnz_lower], input ordering). */
+/* The selected elements of Z_l = A_l^{-1} (Sec. II.A: selected inversion
+ * returns the entries of the inverse on the pattern of H and S, which the
+ * pattern of L contains) at the input entries: out (device, nnz_lower
+ * complex, input ordering) after pxs_selinv; used by tests and for the LDOS
+ * of Sec. II.D.  Errors: PXS_EINVAL for a null handle or output or a shift
+ * outside 0..nshift-1. */
 pxs_status pxs_get_selected(pxs_numeric num, int32_t shift, pxs_c64* out, void* stream);
 /* Z_l[j][i] for every input entry (i, j), i >= j (equal to pxs_get_selected
  * for real pencils). */
@@ -267,8 +279,14 @@ pxs_status pxs_inertia_hermitian(pxs_symbolic sym, const pxs_c64* Hval, const px
                                  int32_t nshift, const double* eps, void* Lbuf, void* work,
                                  int64_t* neg_count, int64_t* info, void* stream);
 
-/* Fused: poles + factor + selinv + pole sums, with the buffers above;
- * shifts/weights (host, nullable) receive the pole table used. */
+/* The density matrix of Sec. II.B in one call: the pole table of eq.
+ * polerho for (beta, dE, mu, P) and nsets weight sets (eq. gammaF), the
+ * factorization and selected inversion of every shift, and the pole sums
+ * Gamma^g = Im sum_l omega_l^g Z_l with their traces (eqs. gammapole, Nmu).
+ * Buffers and outputs as for pxs_factor and pxs_pole_sum (out: device
+ * nsets * nnz_lower; traces: host 2 * nsets; info: host P, nullable);
+ * shifts/weights (host, nullable) receive the pole table used.  Errors: as
+ * pxs_poles, pxs_factor, pxs_pole_sum; PXS_TINY_PIVOT as pxs_factor. */
 pxs_status pxs_density_matrix(pxs_symbolic sym, const double* Hval, const double* Sval,
                               double beta, double dE, double mu, int32_t P, int32_t nsets,
                               void* Lbuf, void* work, double* out, double* traces,

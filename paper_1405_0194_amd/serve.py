@@ -133,7 +133,7 @@ class Server:
         self.used = 0
         self.workers = concurrent.futures.ThreadPoolExecutor(max_workers=max(1, host_workers))
         self.stats = dict(symbolic_hits=0, symbolic_misses=0, plan_hits=0, plan_misses=0,
-                          evictions=0, chunked=0, analyze_s=0.0, inertia_retries=0)
+                          evictions=0, chunked=0, analyze_s=0.0, inertia_retries=0, alloc_retries=0)
 
     # ------------------------------------------------------------------ host side
     def _analyse(self, system, poles):
@@ -227,13 +227,37 @@ class Server:
         need = resident_bytes(a, chunk, req.nsets)
         if not self._make_room(need):
             return None
-        import torch
-        with torch.cuda.device(self.device):
-            r = Resident(a, req.poles, req.nsets, chunk, self.device)
+        r = self._new_resident(a, req, chunk, need)
+        if r is None:
+            return None
         self.residents[rk] = r
         self.used += r.footprint
         self.stats["plan_misses"] += 1
         return r
+
+    def _new_resident(self, a, req, chunk, need):
+        """Allocates a resident; None if the memory is not there yet."""
+        torch = self.torch
+        try:
+            with torch.cuda.device(self.device):
+                return Resident(a, req.poles, req.nsets, chunk, self.device)
+        except torch.OutOfMemoryError:
+            pass
+        # within the budget, but the allocator's free memory is split into
+        # blocks too small: drop the idle residents, return the allocator's
+        # cached blocks to the device and try once more; else wait for
+        # running requests to end
+        self.stats["alloc_retries"] += 1
+        for idle in [k for k in self.residents if not self.residents[k].busy]:
+            self._evict(idle)
+        torch.cuda.empty_cache()
+        if not self._make_room(need):
+            return None
+        try:
+            with torch.cuda.device(self.device):
+                return Resident(a, req.poles, req.nsets, chunk, self.device)
+        except torch.OutOfMemoryError:
+            return None
 
     # -------------------------------------------------------------- execution
     def _start(self, req, r, si, now):
@@ -315,10 +339,11 @@ class Server:
         req._staged = None
         r.busy = False
 
-    def run(self, requests, realtime=True, poll_s=2e-4):
+    def run(self, requests, realtime=True, poll_s=2e-4, log=None, log_every_s=10.0):
         """Serves the requests (arrival times in seconds from the start);
         returns a summary dict.  realtime=False ignores arrival times
-        (saturated throughput)."""
+        (saturated throughput).  log: a text stream for a progress line
+        every log_every_s seconds."""
         torch = self.torch
         reqs = sorted(requests, key=lambda q: q.arrival)
         for i, q in enumerate(reqs):
@@ -328,9 +353,15 @@ class Server:
         active = []   # (req, resident, stream index, event)
         free = list(range(len(self.streams)))
         nxt = 0
+        ndone = 0
         t0 = time.perf_counter()
+        t_log = t0
         while nxt < len(reqs) or waiting or active:
             now = time.perf_counter() - t0
+            if log is not None and time.perf_counter() - t_log >= log_every_s:
+                t_log = time.perf_counter()
+                print(f"# serve: {now:.0f}s, {ndone}/{len(reqs)} done, {len(active)} running, "
+                      f"{len(waiting)} waiting", file=log, flush=True)
             while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= now):
                 if not realtime:
                     reqs[nxt].arrival = 0.0
@@ -347,6 +378,7 @@ class Server:
                     self._finish(req, r, si)
                     free.append(si)
                     progressed = True
+                    ndone += 1
                 else:
                     still.append(item)
             active = still
