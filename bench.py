@@ -464,6 +464,8 @@ def run_serve(args):
     main = runs[loads[-1]] if loads else out["saturated"]
     res = dict(value=round(main["pole_solves_per_s"], 4), ms_per_step=round(1e3 * main["makespan_s"], 3),
                latency_s={"p50": round(main["p50_s"], 4), "p99": round(main["p99_s"], 4)},
+               path_tflops=round(main["path_tflops"], 3),
+               fp64_mfma_pct=round(100.0 * main["path_tflops"] / PEAK_FP64_TFLOPS, 2),
                config={"workload": MULTI["serve"], "requests": len(raw), "kmax": args.kmax,
                        "saturated_req_per_s": round(lam, 4), "loads": loads,
                        "largest_n": max(r["system"].n for r in raw)},

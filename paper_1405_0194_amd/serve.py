@@ -69,6 +69,7 @@ class Request:
     t_admit: float = 0.0
     t_done: float = 0.0
     chunks: int = 1
+    flops: float = 0.0            # algorithmic flops of the request (pole solves + inertia counts)
     key: str = ""
     _staged: object = None        # future of the pinned host copies of H and S values
     _dev: object = None           # device tensors alive until completion
@@ -133,7 +134,8 @@ class Server:
         self.used = 0
         self.workers = concurrent.futures.ThreadPoolExecutor(max_workers=max(1, host_workers))
         self.stats = dict(symbolic_hits=0, symbolic_misses=0, plan_hits=0, plan_misses=0,
-                          evictions=0, chunked=0, analyze_s=0.0, inertia_retries=0, alloc_retries=0)
+                          evictions=0, chunked=0, analyze_s=0.0, inertia_retries=0, alloc_retries=0,
+                          deep_cleans=0)
 
     # ------------------------------------------------------------------ host side
     def _analyse(self, system, poles):
@@ -178,11 +180,19 @@ class Server:
         self.stats["analyze_s"] += secs
         a.bind(self.device)
         self.analyses[key] = a
+        self.used += a.info["map_bytes"]       # the bound maps live on the device
         while len(self.analyses) > self.max_patterns:
-            old, _ = self.analyses.popitem(last=False)
-            for rk in [k for k in self.residents if k[0] == old and not self.residents[k].busy]:
-                self._evict(rk)
+            old = next(iter(self.analyses))
+            self._drop_analysis(old)
         return a
+
+    def _drop_analysis(self, key):
+        """Forgets a pattern's analysis (its maps) and its idle residents;
+        busy residents keep their own reference until they are evicted."""
+        a = self.analyses.pop(key)
+        self.used -= a.info["map_bytes"]
+        for rk in [k for k in self.residents if k[0] == key and not self.residents[k].busy]:
+            self._evict(rk)
 
     def _evict(self, rk):
         r = self.residents.pop(rk)
@@ -275,6 +285,12 @@ class Server:
         req.chunks = (req.poles + r.chunk - 1) // r.chunk
         if req.chunks > 1:
             self.stats["chunked"] += 1
+        info = r.analysis.info
+        # complex shifts: factor + SelInv; real inertia shifts: a real
+        # factorization (2 flops per multiply-add instead of 8)
+        req.flops = req.poles * (info["flops_factor"] + info["flops_selinv"])
+        if req.eps is not None:
+            req.flops += len(req.eps) * info["flops_factor"] / 4.0
         d = {"pinned": (hp, sp)}
         with torch.cuda.stream(st):
             r.H.copy_(hp, non_blocking=True)
@@ -354,6 +370,7 @@ class Server:
         free = list(range(len(self.streams)))
         nxt = 0
         ndone = 0
+        cleaned = False
         t0 = time.perf_counter()
         t_log = t0
         while nxt < len(reqs) or waiting or active:
@@ -398,16 +415,31 @@ class Server:
             if (not progressed and not active and waiting and not self.pending
                     and all(q._staged.done() for q in waiting)):
                 # nothing runs and nothing is being prepared, yet no waiting
-                # request could start: none ever will
-                raise RuntimeError("scheduler stalled: a waiting request can never be admitted")
+                # request could start: free everything idle (residents, the
+                # analyses no waiting request needs, the allocator's cached
+                # blocks) and try again; if that was done already, none ever will
+                if cleaned:
+                    raise RuntimeError("scheduler stalled: a waiting request can never be admitted")
+                keep = {q.key for q in waiting}
+                for rk in [k for k in self.residents if not self.residents[k].busy]:
+                    self._evict(rk)
+                for key in [k for k in self.analyses if k not in keep]:
+                    self._drop_analysis(key)
+                torch.cuda.empty_cache()
+                self.stats["deep_cleans"] += 1
+                cleaned = True
+                continue
+            if progressed:
+                cleaned = False
             if not progressed:
                 time.sleep(poll_s)
         torch.cuda.synchronize()
         makespan = time.perf_counter() - t0
         lat = np.array([q.latency for q in reqs])
         solves = sum(q.poles for q in reqs)
+        flops = sum(q.flops for q in reqs)
         return dict(requests=len(reqs), makespan_s=makespan, req_per_s=len(reqs) / makespan,
-                    pole_solves_per_s=solves / makespan,
+                    pole_solves_per_s=solves / makespan, path_tflops=flops / makespan / 1e12,
                     p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                     mean_s=float(lat.mean()), **self.stats)
 

@@ -13,7 +13,7 @@ from paper_1405_0194_amd import serve
 
 class _FakeAnalysis:
     def __init__(self, nnz, bps, wps):
-        self.info = {"nnz_lower": nnz, "bytes_per_shift": bps}
+        self.info = {"nnz_lower": nnz, "bytes_per_shift": bps, "map_bytes": 4096}
         self._wps = wps
 
     def workspace_size(self, nshift, real=False):
@@ -49,7 +49,7 @@ def _server(budget, share=1.0):
     srv.residents = OrderedDict()
     srv.used = 0
     srv.stats = dict(symbolic_hits=0, symbolic_misses=0, plan_hits=0, plan_misses=0, evictions=0, chunked=0,
-                     analyze_s=0.0, inertia_retries=0, alloc_retries=0)
+                     analyze_s=0.0, inertia_retries=0, alloc_retries=0, deep_cleans=0)
     return srv
 
 
