@@ -210,12 +210,15 @@ class Server:
 
     def chunk_for(self, a, P, nsets):
         """Shifts per pole chunk: all P when the request fits the per-request
-        cap, else the largest even chunk (halving) that does."""
-        cap = max(self.request_cap, 1)
+        cap, else the largest even chunk (halving) that does.  The pattern's
+        bound maps stay on the device while the request runs, so the resident
+        must fit beside them."""
+        room = self.budget - a.info["map_bytes"]
+        cap = max(min(self.request_cap, room), 1)
         c = P
         while c > 2 and resident_bytes(a, c, nsets) > cap:
             c = max(2, (c // 2) & ~1)
-        if resident_bytes(a, c, nsets) > self.budget:
+        if resident_bytes(a, c, nsets) > room:
             raise B.PxsError("Server", B.PXS_ENOMEM, "request does not fit the memory budget")
         return c
 

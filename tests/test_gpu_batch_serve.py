@@ -440,7 +440,7 @@ def test_server_chunks_a_30k_cubic_request(torch_cuda):
     torch.cuda.empty_cache()
     # served in pole chunks
     a1 = B.Analysis.from_system(s)
-    budget = resident_bytes(a1, 10, 2) + 2**20
+    budget = resident_bytes(a1, 10, 2) + a1.info["map_bytes"] + 2**20
     srv = Server(budget_bytes=budget, nstreams=2, keep_outputs=True, max_request_share=1.0)
     req = Request(system=s, mu=mu, poles=P, dE=dE)
     say("case: 30k cubic served in chunks, budget", budget)

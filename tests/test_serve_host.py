@@ -103,7 +103,11 @@ def test_pole_chunk_respects_request_share():
     c = srv.chunk_for(a, 40, 2)
     assert c < 40 and c % 2 == 0
     assert serve.resident_bytes(a, c, 2) <= srv.request_cap
-    srv = _server(budget=full + 10, share=1.0)
+    srv = _server(budget=full + a.info["map_bytes"] + 10, share=1.0)
     assert srv.chunk_for(a, 40, 2) == 40
+    # the pattern's maps stay on the device beside the resident
+    srv = _server(budget=full + 10, share=1.0)
+    c = srv.chunk_for(a, 40, 2)
+    assert c < 40 and serve.resident_bytes(a, c, 2) + a.info["map_bytes"] <= srv.budget
     with pytest.raises(Exception):
         _server(budget=10, share=1.0).chunk_for(a, 40, 2)
