@@ -134,29 +134,36 @@ def mfma_from_counters(workload, counter_dir, command):
     """Per kernel, from one rocprofv3 --pmc run of SQ_INSTS_VALU_MFMA_MOPS_F64
     (FP64 matrix operations / 512), SQ_VALU_MFMA_BUSY_CYCLES, SQ_BUSY_CYCLES
     and GRBM_GUI_ACTIVE: the FP64 MFMA flops the hardware executed per launch
-    and the fraction of the busy shader cycles in which the matrix cores
-    were busy.  Writes profiles/mfma_<workload>.json."""
+    (padding of partial tiles included), their rate over the launch duration,
+    and the fraction of SIMD cycles in which the matrix cores were busy.
+    GRBM_GUI_ACTIVE sums the busy clocks of the 8 XCDs and the MFMA busy
+    cycles sum over the 1,024 SIMDs (256 CUs x 4).  Writes
+    profiles/mfma_<workload>.json."""
+    n_xcd, n_simd = 8, 1024
     per = {}
     for r in _counter_rows(counter_dir):
         base = r["Kernel_Name"].split("<")[0].split("(")[0].strip().split("::")[-1]
         if not base.startswith("k_"):
             continue
-        k = per.setdefault(base, {})
+        k = per.setdefault(base, {"dur": {}})
         k.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        k["dur"][r["Dispatch_Id"]] = (float(r["End_Timestamp"]) - float(r["Start_Timestamp"])) * 1e-9
     out = {"workload": workload, "command": command, "kernels": {}}
     for base, c in sorted(per.items()):
         mops = c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", [])
         busy = c.get("SQ_VALU_MFMA_BUSY_CYCLES", [])
-        sq = c.get("SQ_BUSY_CYCLES", [])
         gui = c.get("GRBM_GUI_ACTIVE", [])
         n = len(mops)
         if not n:
             continue
-        e = {"launches": n, "mfma_flops_per_launch": 512.0 * sum(mops) / n}
-        if busy and sq and sum(sq) > 0:
-            e["mfma_busy_per_sq_busy"] = round(sum(busy) / sum(sq), 4)
-        if gui:
-            e["grbm_gui_active_per_launch"] = sum(gui) / len(gui)
+        flops = 512.0 * sum(mops) / n
+        dur = sum(c["dur"].values()) / len(c["dur"])
+        e = {"launches": n, "mfma_flops_per_launch": flops, "avg_launch_ms": round(dur * 1e3, 4),
+             "mfma_tflops": round(flops / dur / 1e12, 2) if dur > 0 else None}
+        if busy and gui and sum(gui) > 0:
+            clocks = sum(gui) / len(gui) / n_xcd
+            e["mfma_busy_frac"] = round(sum(busy) / len(busy) / (clocks * n_simd), 4)
+            e["clock_ghz"] = round(clocks / dur / 1e9, 3) if dur > 0 else None
         out["kernels"][base] = e
     p = os.path.join(ROOT, "profiles", f"mfma_{workload}.json")
     with open(p, "w") as f:
