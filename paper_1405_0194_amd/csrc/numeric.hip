@@ -78,6 +78,22 @@ __device__ __forceinline__ void st_elem(double* base, int64_t e, cplx v) {
   }
 }
 
+// An operand element, or zero where ok is false: lanes outside the operand
+// read a zero block instead of skipping the load, so every lane issues its
+// load without a branch.  The compiler can then count the loads in flight
+// exactly and the K loop's two-deep prefetch waits only for the older chunk.
+__device__ __align__(16) double kZeroElem[2] = {0.0, 0.0};   // never written
+
+template <bool CPLX>
+__device__ __forceinline__ cplx ld_or_zero(const double* base, int64_t e, bool ok) {
+  const double* q = ok ? base + (CPLX ? 2 : 1) * e : kZeroElem;
+  if (CPLX) {
+    const double2 v = *reinterpret_cast<const double2*>(q);
+    return {v.x, v.y};
+  }
+  return {*q, 0.0};
+}
+
 // --------------------------------------------------------------------------
 // MFMA tile engine: a 256-thread workgroup accumulates a 64 x NTILE tile
 // P[m][n] = sum_k A[m][k] B[k][n] (NTILE = 64 or 128).  The 4 waves are laid
@@ -373,9 +389,9 @@ __device__ __forceinline__ void gemm_pipe(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NT
   auto kat = [&](int c) { return kb + min(c, nc - 1) * KC; };
   const int t = threadIdx.x;
   auto dfetch = [&](cplx& r, int k0) {
-    if constexpr (SC) {
-      if (t < KC) r = gd(k0 + t);
-    }
+    // every thread loads (the lanes of a wave share KC addresses), so the
+    // load is not under a branch; threads t < KC commit it
+    if constexpr (SC) r = gd(k0 + (t & (KC - 1)));
   };
   auto dcommit = [&](Stage<CPLX, NTILE>& st, const cplx& r) {
     if constexpr (SC) {
@@ -755,14 +771,12 @@ __global__ void PXS_LB(TN) k_trsm(Src src) {
   gemm_pipe<CPLX, TN, false>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[c][k]: column k of the diagonal block
-        if (m >= p.wp || kg >= p.wp || m < kg) return cplx{0.0, 0.0};
-        if (m == kg) return cplx{1.0, 0.0};
-        return ld_elem<CPLX>(Ls, dbase + (int64_t)kg * p.ld + m);
+        const cplx v = ld_or_zero<CPLX>(Ls, dbase + (int64_t)kg * p.ld + m, m < p.wp && kg < p.wp && m > kg);
+        return (m == kg && m < p.wp) ? cplx{1.0, 0.0} : v;
       },
       [&](int n, int kg) -> cplx {   // A[i][k]
         const int ig = i0 + n;
-        if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
-        return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
+        return ld_or_zero<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig, kg < p.wp && ig < p.nb);
       },
       RowsFast());
   acc_foreach<CPLX, TN>(acc, [&](int m, int n, cplx v) {
@@ -791,18 +805,15 @@ __global__ void PXS_LB(TN) k_int_update(Src src) {
   gemm_pipe<CPLX, TN, false>(
       acc, s, 0, p.p0,
       [&](int m, int kg) -> cplx {   // L[p0 + c][k] (times d_k on the way to the MFMAs)
-        if (m >= p.wp || kg >= p.p0) return cplx{0.0, 0.0};
-        return ld_elem<CPLX>(Ls, cbase + (int64_t)kg * p.ld + m);
+        return ld_or_zero<CPLX>(Ls, cbase + (int64_t)kg * p.ld + m, m < p.wp && kg < p.p0);
       },
       [&](int n, int kg) -> cplx {   // L[p0 + r][k]
         const int rg = r0 + n;
-        if (kg >= p.p0 || rg >= nrows) return cplx{0.0, 0.0};
-        return ld_elem<CPLX>(Ls, cbase + (int64_t)kg * p.ld + rg);
+        return ld_or_zero<CPLX>(Ls, cbase + (int64_t)kg * p.ld + rg, kg < p.p0 && rg < nrows);
       },
       RowsFast(),
       [&](int kg) -> cplx {          // d_k
-        if (kg >= p.p0) return cplx{0.0, 0.0};
-        return ld_elem<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg);
+        return ld_or_zero<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg, kg < p.p0);
       });
   acc_sub_into<CPLX, TN>(acc, Ls, [&](int m, int n, int64_t& e) {
     const int rg = r0 + n;
@@ -850,18 +861,15 @@ __global__ void PXS_LB(TN) k_update(Src src) {
       acc, s, kb, ke,
       [&](int m, int kg) -> cplx {   // L[j][k] (times d_k on the way to the MFMAs)
         const int jg = j0 + m;
-        if (kg >= ke || jg >= p.nb) return cplx{0.0, 0.0};
-        return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + jg);
+        return ld_or_zero<CPLX>(Ls, rbase + (int64_t)kg * p.ld + jg, kg < ke && jg < p.nb);
       },
       [&](int n, int kg) -> cplx {
         const int ig = i0 + n;
-        if (kg >= ke || ig >= p.nb) return cplx{0.0, 0.0};
-        return ld_elem<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig);
+        return ld_or_zero<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig, kg < ke && ig < p.nb);
       },
       RowsFast(),
       [&](int kg) -> cplx {          // d_k
-        if (kg >= ke) return cplx{0.0, 0.0};
-        return ld_elem<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg);
+        return ld_or_zero<CPLX>(Ls, p.off + (int64_t)kg * p.ld + kg, kg < ke);
       });
   const int64_t* cmap = c.colmap + p.cm;
   const int64_t* cseg = c.colseg + p.cm;
@@ -903,14 +911,12 @@ __global__ void PXS_LB(TN) k_lhat(Src src) {
   gemm_pipe<true, TN, true>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[k][c]: column c of the diagonal block, rows k
-        if (m >= p.wp || kg >= p.wp || kg < m) return cplx{0.0, 0.0};
-        if (kg == m) return cplx{1.0, 0.0};
-        return ld_elem<true>(Ls, dbase + (int64_t)m * p.ld + kg);
+        const cplx v = ld_or_zero<true>(Ls, dbase + (int64_t)m * p.ld + kg, m < p.wp && kg < p.wp && kg > m);
+        return (kg == m && m < p.wp) ? cplx{1.0, 0.0} : v;
       },
       [&](int n, int kg) -> cplx {
         const int ig = i0 + n;
-        if (kg >= p.wp || ig >= p.nb) return cplx{0.0, 0.0};
-        return ld_elem<true>(Ls, rbase + (int64_t)kg * p.ld + ig);
+        return ld_or_zero<true>(Ls, rbase + (int64_t)kg * p.ld + ig, kg < p.wp && ig < p.nb);
       },
       RowsFast());
   acc_foreach<true, TN>(acc, [&](int m, int n, cplx v) {
@@ -941,16 +947,16 @@ __global__ void PXS_LB(TN) k_selinv_off(Src src) {
   gemm_pipe<true, TN, true>(
       acc, s, 0, p.nb,
       [&](int m, int kg) -> cplx {
-        if (m >= p.wp || kg >= p.nb) return cplx{0.0, 0.0};
-        return ld_elem<true>(W, (int64_t)m * p.nb + kg);
+        return ld_or_zero<true>(W, (int64_t)m * p.nb + kg, m < p.wp && kg < p.nb);
       },
       [&](int n, int kg) -> cplx {
         const int ig = i0 + n;
-        if (kg >= p.nb || ig >= p.nb) return cplx{0.0, 0.0};
         const int qk = base + kg, qi = base + ig;
         const int lo = min(qi, qk), hi = max(qi, qk);
-        if (lo >= p.w) return ld_elem<true>(G, (int64_t)(lo - p.w) * p.c + (hi - p.w));
-        return ld_elem<true>(Ls, p.off + (int64_t)lo * p.ld + hi);
+        const bool in_g = lo >= p.w;
+        const double* src = in_g ? G : Ls;
+        const int64_t e = in_g ? (int64_t)(lo - p.w) * p.c + (hi - p.w) : p.off + (int64_t)lo * p.ld + hi;
+        return ld_or_zero<true>(src, e, kg < p.nb && ig < p.nb);
       },
       // both sources are lower triangles stored by column: rows are
       // contiguous for each k when the whole chunk lies on or below the
@@ -1027,12 +1033,10 @@ __global__ void PXS_LB(64) k_selinv_diag_partial(Src src) {
   gemm_pipe<true, TM, true>(
       acc, s, kb, ke,
       [&](int m, int kg) -> cplx {
-        if (m >= p.wp || kg >= ke) return cplx{0.0, 0.0};
-        return ld_elem<true>(Ls, rbase + (int64_t)m * p.ld + kg);
+        return ld_or_zero<true>(Ls, rbase + (int64_t)m * p.ld + kg, m < p.wp && kg < ke);
       },
       [&](int n, int kg) -> cplx {
-        if (n >= p.wp || kg >= ke) return cplx{0.0, 0.0};
-        return ld_elem<true>(W, (int64_t)n * p.nb + kg);
+        return ld_or_zero<true>(W, (int64_t)n * p.nb + kg, n < p.wp && kg < ke);
       },
       KFast());
   double* out = part + 2 * (int64_t)sp * 64 * 64;
