@@ -497,6 +497,8 @@ def main():
     ap.add_argument("--leaf-cols", type=int, default=0)
     ap.add_argument("--selinv-streams", type=int, default=0)
     ap.add_argument("--selinv-chunk", type=int, default=0)
+    ap.add_argument("--sep-cols", type=int, default=-1,
+                    help="max columns of a separator supernode (0: no cut; default: the tuned value)")
     ap.add_argument("--hbm-budget-gib", type=float, default=260.0,
                     help="device memory for factors + workspace; SelInv chunks its shifts beyond it")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -596,10 +598,11 @@ def main():
     dE = 1.0 + abs(mu)
     beta = lattice.BETA_300K
     t_an = time.perf_counter()
-    if args.tile_rows or args.panel_width or args.leaf_cols or args.selinv_streams or args.selinv_chunk:
+    if args.tile_rows or args.panel_width or args.leaf_cols or args.selinv_streams or args.selinv_chunk \
+            or args.sep_cols >= 0:
         a = B.Analysis.from_system(s, tile_rows=args.tile_rows, panel_width=args.panel_width,
                                    leaf_cols=args.leaf_cols, selinv_streams=args.selinv_streams,
-                                   selinv_chunk=args.selinv_chunk)
+                                   selinv_chunk=args.selinv_chunk, sep_cols=max(args.sep_cols, 0))
     else:
         from paper_1405_0194_amd import tune
         a = tune.tuned_analysis(s, lattice.CONFIG_POLES[cfg])

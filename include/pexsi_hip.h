@@ -89,6 +89,11 @@ typedef struct {
   int32_t selinv_streams; /* streams for independent subtrees in selected
                            inversion, 1..8 (0: 4); the library creates them
                            (default priority) on first use */
+  int32_t sep_cols;     /* max columns of a separator supernode: a wider
+                           nested-dissection separator is cut into pieces of
+                           at most this many columns, each a supernode whose
+                           rows below are the union of its own columns'
+                           structures (fewer stored zeros); 0: no cut */
   double reserved1[2];
 } pxs_options;
 

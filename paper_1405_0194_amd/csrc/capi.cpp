@@ -116,6 +116,8 @@ pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, 
   if (opt) {
     o.ordering = opt->ordering;
     if (opt->leaf_cols > 0) o.leaf_cols = opt->leaf_cols;
+    if (opt->sep_cols < 0) return PXS_EINVAL;
+    o.sep_cols = opt->sep_cols;
     if (opt->panel_width > 0) o.panel_width = opt->panel_width;
     if (opt->pivot_tol > 0) o.pivot_tol = opt->pivot_tol;
     if (opt->selinv_chunk < 0) return PXS_EINVAL;

@@ -111,6 +111,7 @@ struct AnalyzeOptions {
   int tile_rows = 64;
   int ordering = 0;
   int leaf_cols = 128;
+  int sep_cols = 0;        // 0: every separator is one supernode
   int panel_width = 64;
   double pivot_tol = 1e-14;
 };

@@ -41,8 +41,8 @@ struct BlockGraph {
 
 class NestedDissection {
  public:
-  NestedDissection(const BlockGraph& g, const double* coords, int leaf_cols)
-      : g_(g), coords_(coords), leaf_(leaf_cols), mark_(g.nv, -1), level_(g.nv, -1) {}
+  NestedDissection(const BlockGraph& g, const double* coords, int leaf_cols, int sep_cols)
+      : g_(g), coords_(coords), leaf_(leaf_cols), sep_(sep_cols), mark_(g.nv, -1), level_(g.nv, -1) {}
 
   // Appends the block order to `order` and one entry per supernode (its
   // blocks, in order) to `snodes`.
@@ -58,6 +58,7 @@ class NestedDissection {
   const BlockGraph& g_;
   const double* coords_;
   int leaf_;
+  int sep_;
   std::vector<int32_t> mark_, level_;
   int32_t stamp_ = 0;
   std::vector<int32_t>* order_ = nullptr;
@@ -73,6 +74,45 @@ class NestedDissection {
     if (v.empty()) return;
     for (int32_t x : v) order_->push_back(x);
     snodes_->push_back(v);
+  }
+
+  // A separator wider than sep_ columns becomes several supernodes of at
+  // most sep_ columns, cut in slabs along its longest extent (coordinates)
+  // or in its current order.  Each piece's rows below are the union of its
+  // own columns' structures, which along a separator grow from the first
+  // column to the last: one supernode over the whole separator stores the
+  // last column's structure for every column.
+  void emit_separator(std::vector<int32_t>& sep) {
+    if (sep_ <= 0 || weight(sep) <= sep_) {
+      emit(sep);
+      return;
+    }
+    if (coords_) {
+      double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+      for (int32_t v : sep)
+        for (int d = 0; d < 3; ++d) {
+          lo[d] = std::min(lo[d], coords_[3 * v + d]);
+          hi[d] = std::max(hi[d], coords_[3 * v + d]);
+        }
+      int ax = 0;
+      for (int d = 1; d < 3; ++d)
+        if (hi[d] - lo[d] > hi[ax] - lo[ax]) ax = d;
+      std::stable_sort(sep.begin(), sep.end(), [&](int32_t a, int32_t b) {
+        return coords_[3 * a + ax] < coords_[3 * b + ax];
+      });
+    }
+    std::vector<int32_t> piece;
+    int64_t w = 0;
+    for (int32_t v : sep) {
+      if (!piece.empty() && w + g_.wgt[v] > sep_) {
+        emit(piece);
+        piece.clear();
+        w = 0;
+      }
+      piece.push_back(v);
+      w += g_.wgt[v];
+    }
+    emit(piece);
   }
 
   // BFS inside the vertex subset tagged with `tag`; returns visit order and
@@ -140,7 +180,7 @@ class NestedDissection {
     }
     recurse(std::move(L), depth + 1);
     recurse(std::move(R), depth + 1);
-    emit(sep);
+    emit_separator(sep);
   }
 
   bool split_geometric(std::vector<int32_t>& verts, std::vector<int32_t>& L,
@@ -307,7 +347,7 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
     }
     if (!cur.empty()) sblocks.push_back(cur);
   } else {
-    NestedDissection nd(g, coords, std::max(1, opt.leaf_cols));
+    NestedDissection nd(g, coords, std::max(1, opt.leaf_cols), opt.sep_cols);
     nd.run(border, sblocks);
   }
   if ((int32_t)border.size() != nblk) { msg = "internal: ordering lost blocks"; return -1; }

@@ -140,6 +140,8 @@ def test_inertia_counts_match_eigenvalues(torch_cuda):
     ("honeycomb", (8, 7), 13, 3.0, dict(selinv_streams=1)),
     ("cubic", (6, 5, 5), 13, 2.0, dict(selinv_streams=8, selinv_chunk=13)),
     ("chain", 301, 3, 2.0, dict(panel_width=7, leaf_cols=33, tile_rows=128)),
+    ("cubic", (6, 5, 5), 13, 2.0, dict(sep_cols=130)),
+    ("cubic", (5, 5, 6), 5, 2.0, dict(sep_cols=20, panel_width=16, selinv_chunk=9)),
 ])
 def test_lattice_parity_several_tiles(torch_cuda, kind, dims, orb, cut, akw):
     torch = torch_cuda

@@ -127,6 +127,37 @@ def test_symbolic_small_honeycomb_graph_ordering():
     assert a.info["nnz_L_exact"] == int(Lx.sum())
 
 
+@pytest.mark.parametrize("sep_cols", [4, 9, 30])
+def test_separator_pieces_keep_exact_pattern(sep_cols):
+    # wide separators cut into supernodes of at most sep_cols columns: still
+    # a relaxed pattern that contains the exact one, the same exact counts,
+    # and no more stored entries than one supernode per separator
+    s = lattice.make_system("cubic", (5, 5, 4), 2, 2.0, 11, periodic=False)
+    whole = B.Analysis.from_system(s, leaf_cols=16)
+    cut = B.Analysis.from_system(s, leaf_cols=16, sep_cols=sep_cols)
+    P = osym.dense_pattern_from_lower_csc(s.n, s.colptr, s.rowind)
+    Lx = _check_symbolic(cut, P)
+    assert cut.info["nnz_L_exact"] == int(Lx.sum())
+    ex = cut.export()
+    widths = np.diff(ex["super_ptr"])
+    assert cut.info["nsuper"] > whole.info["nsuper"]
+    # a piece is wider than sep_cols only when one atom block alone is
+    assert np.all((widths <= max(sep_cols, s.orb)) | (widths <= 16))
+    assert cut.info["nnz_L"] <= whole.info["nnz_L"]
+    assert cut.info["bytes_per_shift"] <= whole.info["bytes_per_shift"]
+    ck = Lx.sum(axis=0) - 1                 # exact counts of the cut ordering
+    assert cut.info["flops_factor"] == pytest.approx(8.0 * np.sum(ck * (ck + 1) / 2.0))
+    assert cut.info["flops_selinv"] == pytest.approx(8.0 * np.sum(ck * ck + ck))
+    assert sum(cut.info["macs_exact"]) == pytest.approx(
+        (cut.info["flops_factor"] + cut.info["flops_selinv"]) / 8.0, rel=1e-12)
+
+
+def test_negative_separator_width_rejected():
+    s = lattice.make_system("cubic", (3, 3, 3), 1, 1.0, 2, periodic=False)
+    with pytest.raises(B.PxsError):
+        B.Analysis.from_system(s, sep_cols=-1)
+
+
 def test_nested_dissection_reduces_fill_on_grid():
     # 2D grid: nested dissection must beat the natural (banded) order
     s = lattice.make_system("cubic", (16, 16, 1), 1, 1.0, 9, periodic=False)

@@ -26,3 +26,19 @@ def test_tuned_options_are_applied(tmp_path):
     t = tune.tuned_analysis(s, 40, cache=cache)
     assert t.info["npanel"] > a.info["npanel"]          # narrower panels
     assert tune.options_for(s, 80, cache=cache) == tune.DEFAULTS   # untuned bucket
+
+
+def test_separator_cut_taken_in_3d_not_in_2d():
+    # a 3D bulk: the cut removes stored zeros and is taken; a 2D sheet: the
+    # separators' columns share their structure and the cut is left out
+    cube = lattice.make_system("cubic", (10, 10, 10), 13, 2.0, 7)
+    a = tune.with_separator_cut(cube, B.Analysis.from_system(cube))
+    assert a.options["sep_cols"] == tune.SEP_COLS
+    whole = B.Analysis.from_system(cube)
+    assert a.info["nnz_L"] <= (1.0 - tune.CUT_MIN_GAIN) * whole.info["nnz_L"]
+    assert a.info["bytes_per_shift"] < whole.info["bytes_per_shift"]
+    sheet = lattice.make_system("honeycomb", (20, 20), 13, 3.0, 7)
+    b = tune.with_separator_cut(sheet, B.Analysis.from_system(sheet))
+    assert b.options["sep_cols"] == 0
+    # the tuned analysis applies the same rule
+    assert tune.tuned_analysis(cube, 60, cache={}).options["sep_cols"] == tune.SEP_COLS
