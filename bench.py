@@ -499,7 +499,7 @@ def main():
     ap.add_argument("--selinv-chunk", type=int, default=0)
     ap.add_argument("--sep-cols", type=int, default=-1,
                     help="max columns of a separator supernode (0: no cut; default: the tuned value)")
-    ap.add_argument("--hbm-budget-gib", type=float, default=260.0,
+    ap.add_argument("--hbm-budget-gib", type=float, default=270.0,
                     help="device memory for factors + workspace; SelInv chunks its shifts beyond it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for scaling the HBM byte counters)")

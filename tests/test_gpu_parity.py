@@ -283,7 +283,7 @@ def _diag_identity_residual(system, w, z):
 
 
 # device memory the benchmark gives factors + workspace (bench.py --hbm-budget-gib)
-BENCH_BUDGET = int(260.0 * 2**30)
+BENCH_BUDGET = int(270.0 * 2**30)
 
 
 def _full_size_check(torch, cfg):
@@ -365,7 +365,8 @@ def test_full_size_honeycomb_bench_configuration(torch_cuda):
 
 def test_full_size_cubic_configuration(torch_cuda):
     """The cubic bulk (N=22,464, 80 poles, mu inside the dense spectrum) at
-    full size: 187 GiB of factors, SelInv in the benchmark's shift chunks."""
+    full size: 145 GiB of factors (separators cut at 832 columns), SelInv in
+    the benchmark's shift chunks (40 under 270 GiB)."""
     _full_size_check(torch_cuda, 2)
 
 
