@@ -635,10 +635,11 @@ constexpr int NTD = 512;
 
 template <bool CPLX, class Src>
 __global__ void __launch_bounds__(NTD) k_diag(Src src) {
-  __shared__ double a_re[64][LDP];   // a[col][row]: working matrix, then L^{-1} (strict lower)
+  // a[col][row], row > col: the working matrix, then L^{-1}; L is kept in
+  // the other strict triangle, a[row][col] = L[row][col] (one array, 68 KB
+  // of LDS, so a workgroup fits on a CU beside one of the matrix kernels)
+  __shared__ double a_re[64][LDP];
   __shared__ double a_im[CPLX ? 64 : 1][LDP];
-  __shared__ double l_re[64][LDP];   // l[col][row]: L (strict lower)
-  __shared__ double l_im[CPLX ? 64 : 1][LDP];
   __shared__ double dd_re[2][64];    // running diagonal, double-buffered by step parity
   __shared__ double dd_im[2][CPLX ? 64 : 1];
   __shared__ double pv_re[64];       // pivots d_k
@@ -668,8 +669,8 @@ __global__ void __launch_bounds__(NTD) k_diag(Src src) {
   if (t > 0 && t < wp) {
     const cplx d0{dd_re[0][0], CPLX ? dd_im[0][0] : 0.0};
     const cplx v = cmul(cplx{a_re[0][t], CPLX ? a_im[0][t] : 0.0}, inv(d0));
-    l_re[0][t] = v.re;
-    if (CPLX) l_im[0][t] = v.im;
+    a_re[t][0] = v.re;
+    if (CPLX) a_im[t][0] = v.im;
   }
   __syncthreads();
   const double wabs = sqrt(c.shifts[2 * sh] * c.shifts[2 * sh] + c.shifts[2 * sh + 1] * c.shifts[2 * sh + 1]);
@@ -688,11 +689,11 @@ __global__ void __launch_bounds__(NTD) k_diag(Src src) {
       if (CPLX) pv_im[k] = dk.im;
     }
     if (r > k && r < wp) {
-      const cplx lrk{l_re[k][r], CPLX ? l_im[k][r] : 0.0};
+      const cplx lrk{a_re[r][k], CPLX ? a_im[r][k] : 0.0};
       const cplx dl = cmul(dk, lrk);                 // d_k L[r][k]
       // trailing columns j in (k+1, r): off-diagonal entries of A
       for (int j = k + 2 + cg; j < r; j += NTD / 64) {
-        const cplx f = cmul(dl, cplx{l_re[k][j], CPLX ? l_im[k][j] : 0.0});
+        const cplx f = cmul(dl, cplx{a_re[j][k], CPLX ? a_im[j][k] : 0.0});
         a_re[j][r] -= f.re;
         if (CPLX) a_im[j][r] -= f.im;
       }
@@ -704,14 +705,14 @@ __global__ void __launch_bounds__(NTD) k_diag(Src src) {
       }
       if (cg == 1 && r > k + 1) {
         // look-ahead: L[r][k+1] with d_{k+1} formed from the previous values
-        const cplx lk1{l_re[k][k + 1], CPLX ? l_im[k][k + 1] : 0.0};
+        const cplx lk1{a_re[k + 1][k], CPLX ? a_im[k + 1][k] : 0.0};
         const cplx dk1n = cmul(cmul(dk, lk1), lk1);
         const cplx dk1{dd_re[cur][k + 1] - dk1n.re, CPLX ? dd_im[cur][k + 1] - dk1n.im : 0.0};
         const cplx f = cmul(dl, lk1);
         const cplx arn{a_re[k + 1][r] - f.re, CPLX ? a_im[k + 1][r] - f.im : 0.0};
         const cplx v = cmul(arn, inv(dk1));
-        l_re[k + 1][r] = v.re;
-        if (CPLX) l_im[k + 1][r] = v.im;
+        a_re[r][k + 1] = v.re;
+        if (CPLX) a_im[r][k + 1] = v.im;
       }
       // inverse: columns t < k of X get the elimination of column k
       for (int tc = cg; tc < k; tc += NTD / 64) {
