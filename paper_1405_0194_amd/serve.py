@@ -360,9 +360,10 @@ class Server:
 
     def run(self, requests, realtime=True, poll_s=2e-4, log=None, log_every_s=10.0):
         """Serves the requests (arrival times in seconds from the start);
-        returns a summary dict.  realtime=False ignores arrival times
-        (saturated throughput).  log: a text stream for a progress line
-        every log_every_s seconds."""
+        returns a summary dict (its counters cover this call only; caches
+        and residents carry over between calls).  realtime=False ignores
+        arrival times (saturated throughput).  log: a text stream for a
+        progress line every log_every_s seconds."""
         torch = self.torch
         reqs = sorted(requests, key=lambda q: q.arrival)
         for i, q in enumerate(reqs):
@@ -374,6 +375,7 @@ class Server:
         nxt = 0
         ndone = 0
         cleaned = False
+        stats0 = dict(self.stats)   # the summary counts this run only
         t0 = time.perf_counter()
         t_log = t0
         while nxt < len(reqs) or waiting or active:
@@ -444,7 +446,7 @@ class Server:
         return dict(requests=len(reqs), makespan_s=makespan, req_per_s=len(reqs) / makespan,
                     pole_solves_per_s=solves / makespan, path_tflops=flops / makespan / 1e12,
                     p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                    mean_s=float(lat.mean()), **self.stats)
+                    mean_s=float(lat.mean()), **{k: v - stats0[k] for k, v in self.stats.items()})
 
     def close(self):
         self.workers.shutdown(wait=True)
