@@ -282,6 +282,46 @@ def per_pole_sample(a, H, S, beta, dE, mu, P, nsample):
     return (time.perf_counter() - t) / nsample
 
 
+def pole_groups_leg(a, H, S, beta, dE, mu, P, groups, batched_value, reps=3):
+    """The same density matrix with its P poles in `groups` groups, each a
+    captured graph plan on a stream of its own (pole table on the device),
+    outputs added: the top of the tree of one group overlaps the wide levels
+    of the others.  At most 4 groups run at once (4 hardware queues)."""
+    import numpy as np
+    import torch
+    from paper_1405_0194_amd import binding as B
+    if P % groups:
+        return None
+    g = P // groups
+    sh, wt = B.poles(beta, dE, mu, P, 2)
+    wt = np.asarray(wt).reshape(2, P)
+    dev = H.device
+    streams = [torch.cuda.Stream(device=dev) for _ in range(groups)]
+    plans = [B.Plan(a, H, S, g, nsets=2) for _ in range(groups)]
+    shd = [torch.from_numpy(np.ascontiguousarray(sh[i * g:(i + 1) * g])).to(dev) for i in range(groups)]
+    wtd = [torch.from_numpy(np.ascontiguousarray(wt[:, i * g:(i + 1) * g]).reshape(-1)).to(dev)
+           for i in range(groups)]
+
+    def run():
+        for i in range(groups):
+            plans[i].run_device(shd[i], wtd[i], stream=streams[i])
+        for st in streams:
+            st.synchronize()
+    torch.cuda.synchronize()
+    run()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        run()
+        ts.append(time.perf_counter() - t)
+    sec = float(np.median(ts))
+    out = {"groups": groups, "poles_per_group": g, "ms_per_density_matrix": round(1e3 * sec, 3),
+           "pole_solves_per_s": round(P / sec, 4), "vs_one_batch": round(P / sec / batched_value, 4)}
+    del plans
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_batch(args):
     import torch
     from paper_1405_0194_amd import lattice, tune
@@ -500,6 +540,8 @@ def main():
     ap.add_argument("--compare-perpole", type=int, default=4,
                     help="also time the plain per-pole loop on this many shifts (0: skip)")
     ap.add_argument("--no-chain", action="store_true", help="skip the chain-workload leg")
+    ap.add_argument("--pole-groups", type=int, default=4,
+                    help="also time the poles in this many graph-plan groups on separate streams (0: skip)")
     ap.add_argument("--tile-rows", type=int, default=0, help="rows per tile of the panel products (64/128)")
     ap.add_argument("--panel-width", type=int, default=0)
     ap.add_argument("--leaf-cols", type=int, default=0)
@@ -765,6 +807,8 @@ def main():
                                 "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)})
     if not args.no_chain:
         res["chain"] = chain_leg()
+    if args.pole_groups > 1:
+        res["pole_groups"] = pole_groups_leg(a, H, S, beta, dE, mu, P, args.pole_groups, value)
     if args.compare_perpole:
         del f
         sec = per_pole_sample(a, H, S, beta, dE, mu, P, args.compare_perpole)
