@@ -547,6 +547,9 @@ def main():
     ap.add_argument("--leaf-cols", type=int, default=0)
     ap.add_argument("--selinv-streams", type=int, default=0)
     ap.add_argument("--selinv-chunk", type=int, default=0)
+    ap.add_argument("--selinv-fused", type=int, default=-1,
+                    help="1: SelInv subtree lanes fused on one stream, 0: one stream per subtree "
+                         "(default: the tuned choice)")
     ap.add_argument("--sep-cols", type=int, default=-1,
                     help="max columns of a separator supernode (0: no cut; default: the tuned value)")
     ap.add_argument("--hbm-budget-gib", type=float, default=270.0,
@@ -656,6 +659,8 @@ def main():
     else:
         from paper_1405_0194_amd import tune
         a = tune.tuned_analysis(s, lattice.CONFIG_POLES[cfg])
+    if args.selinv_fused >= 0 and a.options.get("selinv_fused", 0) != args.selinv_fused:
+        a = B.Analysis.from_system(s, **{**a.options, "selinv_fused": args.selinv_fused})
     # SelInv works on shift chunks when the whole batch's workspace would not
     # fit beside the factors (the cubic bulk: 201 GB of factors for 80 shifts)
     if not args.selinv_chunk:

@@ -94,6 +94,12 @@ typedef struct {
                            at most this many columns, each a supernode whose
                            rows below are the union of its own columns'
                            structures (fewer stored zeros); 0: no cut */
+  int32_t selinv_fused; /* 1: selected inversion runs the subtrees of the
+                           selinv_streams assignment as lanes of one stream,
+                           each launch taking the next operation of every
+                           lane that has one of its kind ready (one grid, no
+                           library streams, also inside stream captures);
+                           0 (default): one stream per subtree */
   double reserved1[2];
 } pxs_options;
 

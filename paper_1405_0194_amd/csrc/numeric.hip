@@ -590,6 +590,16 @@ struct PanelGroup {
   int32_t n;
 };
 
+// LaneGroup: the same as PanelGroup for at most MAX_LANES panels whose items
+// travel in the kernel arguments (no device table, so a stream capture
+// records them like any other launch): the fused selected inversion of the
+// subtree lanes of one system.
+constexpr int MAX_LANES = 8;
+struct LaneGroup {
+  GroupItem it[MAX_LANES];
+  int32_t n;
+};
+
 // remap: XCD-aware order (else the plain one); bx = tile, by = shift
 __device__ __forceinline__ void locate(const OnePanel& src, Common& c, PanelK& p, int& bx, int& by, bool remap) {
   c = src.c;
@@ -618,6 +628,20 @@ __device__ __forceinline__ void locate(const PanelGroup& src, Common& c, PanelK&
   const int64_t local = lid - it.start;
   bx = (int)(local % it.tiles);
   by = (int)(local / it.tiles);
+}
+
+__device__ __forceinline__ void locate(const LaneGroup& src, Common& c, PanelK& p, int& bx, int& by, bool remap) {
+  int lx = (int)blockIdx.x, ly = 0;
+  if (remap) xcd_remap(lx, ly);   // grid (total, 1)
+  int i = 0;                      // the last item starting at or before lx
+  for (int q = 1; q < src.n; ++q)
+    if (src.it[q].start <= lx) i = q;
+  const GroupItem& it = src.it[i];
+  c = it.c;
+  p = it.p;
+  const int local = lx - (int)it.start;
+  bx = local % it.tiles;
+  by = local / it.tiles;
 }
 
 // Dense LDL^T of the panel's wp x wp diagonal block in LDS, with L_pp^{-1}
@@ -1613,8 +1637,183 @@ int selinv_streams_ready(const Symbolic& S) {
 
 int selinv_event_count(const Symbolic& S) { return S.nsuper + S.sel_nstreams + 1; }
 
+namespace {
+
+// Selected inversion with the subtree lanes fused (sel_fused).  The
+// supernodes keep the lanes of the stream assignment (sel_stream) and each
+// lane its own workspace regions, as on separate streams; the operations of
+// a lane (per supernode from the root down: the Z_CC gather, then per panel
+// from the last: L-hat, off-diagonal product, diagonal partials, diagonal
+// final) run in their order.  Every launch on the caller's stream takes the
+// next operation of each lane whose next operation is of one kind and ready
+// -- the first operation of a supernode whose parent is on another lane
+// waits until the parent's last operation was in an earlier launch -- and
+// runs them as one grid (LaneGroup); the kind is that of the ready lane with
+// the most operations left.  Some lane is always ready: the one whose next
+// supernode is the highest-numbered, since its parent (a higher number) is
+// already done.  Each panel operation computes what it computes on a stream
+// of its own, so the results are the bits of the other paths.
+enum LaneKind : int32_t { LK_GATHER, LK_LHAT, LK_OFF, LK_DPART, LK_DFIN };
+
+struct LaneOp {
+  int32_t kind;
+  int32_t J;
+  bool first;   // first operation of supernode J
+  bool last;    // last operation of J
+  GroupItem it;
+  double work, bytes, stored;   // profile figures (ProfScope)
+};
+
+int lane_launch(int32_t kind, int TR, const LaneGroup& g, int64_t blocks, hipStream_t st) {
+  const dim3 grid((unsigned)blocks);
+  switch (kind) {
+    case LK_GATHER: hipLaunchKernelGGL(k_gather_cc<LaneGroup>, grid, dim3(NT), 0, st, g); break;
+    case LK_LHAT:
+      if (TR == 64) hipLaunchKernelGGL((k_lhat<64, LaneGroup>), grid, dim3(NT), 0, st, g);
+      else hipLaunchKernelGGL((k_lhat<128, LaneGroup>), grid, dim3(NT), 0, st, g);
+      break;
+    case LK_OFF:
+      if (TR == 64) hipLaunchKernelGGL((k_selinv_off<64, LaneGroup>), grid, dim3(NT), 0, st, g);
+      else hipLaunchKernelGGL((k_selinv_off<128, LaneGroup>), grid, dim3(NT), 0, st, g);
+      break;
+    case LK_DPART: hipLaunchKernelGGL(k_selinv_diag_partial<LaneGroup>, grid, dim3(NT), 0, st, g); break;
+    case LK_DFIN: hipLaunchKernelGGL(k_selinv_diag_final<LaneGroup>, grid, dim3(NTF), 0, st, g); break;
+    default: return (int)hipErrorInvalidValue;
+  }
+  PXS_CHECK_LAUNCH();
+  return 0;
+}
+
+const int kLaneClass[5] = {KC_GATHER, KC_LHAT, KC_SELINV_OFF, KC_SELINV_DIAG, KC_NONE};
+
+int run_selinv_lanes(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st) {
+  const int NL = S.sel_nstreams;
+  if (NL < 1 || NL > MAX_LANES) return (int)hipErrorInvalidValue;
+  const int ns = S.nsuper;
+  const int TR = S.tile_rows;
+  const int chunk = (S.selinv_chunk > 0 && S.selinv_chunk < nshift) ? S.selinv_chunk : nshift;
+  // workspace views as on NL streams (selinv_work_bytes)
+  std::vector<Common> cs(NL, make_common(S, L, work));
+  int64_t gofs = S.work_fixed + (int64_t)nshift * NL * S.work_per_shift;
+  for (int q = 0; q < NL; ++q) {
+    cs[q].wfix = S.work_fixed + (int64_t)q * nshift * S.work_per_shift;
+    cs[q].G = (double*)((char*)work + gofs);
+    cs[q].gstride = S.gather_bytes[q] / 8;
+    gofs += (int64_t)chunk * S.gather_bytes[q];
+  }
+  std::vector<int> pfirst(ns, 0);
+  for (int ip = (int)S.panels.size() - 1; ip >= 0; --ip) pfirst[S.panels[ip].J] = ip;
+  std::vector<std::vector<LaneOp>> lane(NL);
+  std::vector<int64_t> done(ns);   // launch of J's last operation, -1 before it
+  for (int sh0 = 0; sh0 < nshift; sh0 += chunk) {
+    const int nsh = std::min(chunk, nshift - sh0);
+    for (auto& v : lane) v.clear();
+    for (int J = ns - 1; J >= 0; --J) {
+      const int q = S.sel_stream[J];
+      std::vector<LaneOp>& ops = lane[q];
+      const size_t n0 = ops.size();
+      auto add = [&](int32_t kind, const PanelK& k, int64_t tiles, double w, double b, double s) {
+        LaneOp o;
+        o.kind = kind;
+        o.J = J;
+        o.first = ops.size() == n0;
+        o.last = false;
+        o.it.c = cs[q];
+        o.it.p = k;
+        o.it.start = 0;
+        o.it.tiles = (int32_t)tiles;
+        o.it.nsh = nsh;
+        o.work = w;
+        o.bytes = b;
+        o.stored = s;
+        ops.push_back(o);
+      };
+      const int first = pfirst[J];
+      int last = first;
+      while (last + 1 < (int)S.panels.size() && S.panels[last + 1].J == J) ++last;
+      PanelK g = panel_args(S, S.panels[last]);
+      g.sh0 = sh0;
+      if (g.c > 0) {
+        const int64_t nt = (g.c + TM - 1) / TM;
+        const double gb = (32.0 * nsh + 4.0) * 0.5 * g.c * (g.c + 1);
+        add(LK_GATHER, g, nt * (nt + 1) / 2, gb, gb, gb);
+      }
+      for (int ip = last; ip >= first; --ip) {
+        PanelK k = panel_args(S, S.panels[ip]);
+        k.sh0 = sh0;
+        const PanelMacs& xm = S.xm_panel[ip];
+        if (k.nb > 0) {
+          const int64_t nt = (k.nb + TR - 1) / TR;
+          add(LK_LHAT, k, nt, 0.0, 16.0 * nsh * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)),
+              8.0 * nsh * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
+          add(LK_OFF, k, nt, 8.0 * nsh * xm.off, 16.0 * nsh * (0.5 * k.nb * (k.nb + 1) + 2.0 * k.nb * k.wp),
+              8.0 * nsh * (double)k.nb * k.nb * k.wp);
+          add(LK_DPART, k, k.split, 8.0 * nsh * xm.sdiag, 16.0 * nsh * (2.0 * k.nb * k.wp + (double)k.wp * k.wp),
+              8.0 * nsh * (double)k.nb * k.wp * k.wp);
+        }
+        add(LK_DFIN, k, 1, 0.0, 0.0, 0.0);
+      }
+      ops.back().last = true;
+    }
+    std::fill(done.begin(), done.end(), (int64_t)-1);
+    std::vector<size_t> pos(NL, 0);
+    int64_t nl = 0;   // launches of this chunk so far
+    auto ready = [&](int q) {
+      if (pos[q] >= lane[q].size()) return false;
+      const LaneOp& o = lane[q][pos[q]];
+      if (!o.first) return true;
+      const int P = S.sparent[o.J];
+      return P < 0 || S.sel_stream[P] == q || (done[P] >= 0 && done[P] < nl);
+    };
+    for (;;) {
+      int lead = -1;
+      size_t most = 0;
+      for (int q = 0; q < NL; ++q) {
+        if (!ready(q)) continue;
+        const size_t left = lane[q].size() - pos[q];
+        if (left > most) {
+          most = left;
+          lead = q;
+        }
+      }
+      if (lead < 0) break;
+      const int32_t kind = lane[lead][pos[lead]].kind;
+      LaneGroup grp;
+      grp.n = 0;
+      int64_t start = 0;
+      double w = 0.0, b = 0.0, s = 0.0;
+      for (int q = 0; q < NL; ++q) {
+        if (!ready(q) || lane[q][pos[q]].kind != kind) continue;
+        const LaneOp& o = lane[q][pos[q]];
+        GroupItem it = o.it;
+        it.start = start;
+        start += (int64_t)it.tiles * it.nsh;
+        grp.it[grp.n++] = it;
+        w += o.work;
+        b += o.bytes;
+        s += o.stored;
+        if (o.last) done[o.J] = nl;
+        ++pos[q];
+      }
+      if (start > (int64_t)INT32_MAX) return (int)hipErrorInvalidConfiguration;
+      {
+        ProfScope ps(kLaneClass[kind], st, w, b, s);
+        const int e = lane_launch(kind, TR, grp, start, st);
+        if (e) return e;
+      }
+      ++nl;
+    }
+    for (int q = 0; q < NL; ++q)
+      if (pos[q] != lane[q].size()) return (int)hipErrorUnknown;   // unreachable: some lane is always ready
+  }
+  return 0;
+}
+
+}  // namespace
+
 int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st,
                hipEvent_t* events, bool inorder) {
+  if (S.sel_fused && !inorder && S.sel_nstreams > 1) return run_selinv_lanes(S, nshift, L, work, st);
   // inside a stream capture everything runs on the capturing stream: the
   // subtree streams are used by eager runs only
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;

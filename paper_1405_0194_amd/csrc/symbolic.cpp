@@ -716,6 +716,7 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
     }
   }
   S.selinv_chunk = std::max(0, opt.selinv_chunk);
+  S.sel_fused = opt.selinv_fused ? 1 : 0;
   S.tile_rows = (opt.tile_rows == 128) ? 128 : 64;
   return 0;
 }

@@ -142,6 +142,8 @@ def test_inertia_counts_match_eigenvalues(torch_cuda):
     ("chain", 301, 3, 2.0, dict(panel_width=7, leaf_cols=33, tile_rows=128)),
     ("cubic", (6, 5, 5), 13, 2.0, dict(sep_cols=130)),
     ("cubic", (5, 5, 6), 5, 2.0, dict(sep_cols=20, panel_width=16, selinv_chunk=9)),
+    ("cubic", (6, 5, 5), 13, 2.0, dict(selinv_fused=1)),
+    ("honeycomb", (8, 7), 13, 3.0, dict(selinv_fused=1, selinv_streams=8, selinv_chunk=11, tile_rows=128)),
 ])
 def test_lattice_parity_several_tiles(torch_cuda, kind, dims, orb, cut, akw):
     torch = torch_cuda
@@ -370,18 +372,20 @@ def test_full_size_cubic_configuration(torch_cuda):
     _full_size_check(torch_cuda, 2)
 
 
-def test_graph_plan_replays_match_eager(torch_cuda):
+@pytest.mark.parametrize("fused", [0, 1])
+def test_graph_plan_replays_match_eager(torch_cuda, fused):
     """The captured graph replayed several times (with eager library work and
     synchronisations in between, new pole tables and new H values) gives the
-    eager result bit for bit every time."""
+    eager result bit for bit every time (SelInv lanes fused into the
+    capturing stream, or that stream alone)."""
     torch = torch_cuda
     from paper_1405_0194_amd import binding as B
     s = lattice.make_system("honeycomb", (6, 5), 13, 3.0, 31)
-    a = B.Analysis.from_system(s)
+    a = B.Analysis.from_system(s, selinv_fused=fused)
     H = _dev(torch, s.hval)
     S = _dev(torch, s.sval)
     P = 20
-    say("case: graph plan replays")
+    say("case: graph plan replays, fused lanes", fused)
     plan = B.Plan(a, H, S, P, nsets=2)
     rng = np.random.default_rng(2)
     for rep in range(4):
@@ -401,10 +405,11 @@ def test_graph_plan_replays_match_eager(torch_cuda):
 
 def test_results_do_not_depend_on_the_subtree_streams(torch_cuda):
     """Eager factorization and selected inversion on 1, 2, 4 or 8 subtree
-    streams (and the in-order path of a single stream) give the same
-    factors, selected inverses, pole sums, traces and inertia counts bit for
-    bit: the supernodes are issued in one order on every path and every
-    entry receives its scatters in that order."""
+    streams (and the in-order path of a single stream), or with 4 or 8
+    subtree lanes fused on one stream, give the same factors, selected
+    inverses, pole sums, traces and inertia counts bit for bit: the
+    supernodes are issued in one order on every path and every entry
+    receives its scatters in that order."""
     torch = torch_cuda
     from paper_1405_0194_amd import binding as B
     s = lattice.make_system("honeycomb", (9, 8), 13, 3.0, 77)
@@ -414,9 +419,9 @@ def test_results_do_not_depend_on_the_subtree_streams(torch_cuda):
     sh, wt = B.poles(BETA, 1.0, 0.0, P, 2)
     eps = np.array([-0.3, -0.01, 0.0, 0.2])
     ref = None
-    for ns in (1, 2, 4, 8):
-        say("case: subtree streams", ns, "N", s.n)
-        a = B.Analysis.from_system(s, selinv_streams=ns)
+    for ns, fused in ((1, 0), (2, 0), (4, 0), (8, 0), (4, 1), (8, 1)):
+        say("case: subtree streams", ns, "fused lanes", fused, "N", s.n)
+        a = B.Analysis.from_system(s, selinv_streams=ns, selinv_fused=fused)
         f = B.Factorization(a, H, S, sh)
         d = f.diag(5).cpu().numpy().copy()
         f.selinv()
@@ -429,7 +434,7 @@ def test_results_do_not_depend_on_the_subtree_streams(torch_cuda):
             ref = got
             continue
         for x, y in zip(got, ref):
-            assert np.array_equal(np.asarray(x), np.asarray(y)), ns
+            assert np.array_equal(np.asarray(x), np.asarray(y)), (ns, fused)
 
 
 def test_maximum_batch_of_shifts(torch_cuda):

@@ -305,3 +305,18 @@ def test_exact_macs_per_kernel_class_atom_blocks():
     Lx = osym.fill_pattern(osym.permute(Pd, a.export()["perm"]))
     want = _exact_macs_by_class(a, Lx, 4)
     assert np.allclose(np.array(a.info["macs_exact"]), want, rtol=1e-12, atol=0)
+
+
+def test_fused_selinv_option_values():
+    """selinv_fused takes 0 or 1; it leaves the structure, the sizes and the
+    workspace of the analysis unchanged (the fused lanes use the regions of
+    the subtree streams)."""
+    s = lattice.make_system("honeycomb", (6, 6), 4, 3.0, 3)
+    a0 = B.Analysis.from_system(s)
+    a1 = B.Analysis.from_system(s, selinv_fused=1)
+    for k in ("nnz_L", "nsuper", "npanel", "bytes_per_shift", "work_bytes", "gather_per_shift"):
+        assert a0.info[k] == a1.info[k], k
+    assert a0.workspace_size(20) == a1.workspace_size(20)
+    for bad in (-1, 2):
+        with pytest.raises(B.PxsError):
+            B.Analysis.from_system(s, selinv_fused=bad)
