@@ -98,8 +98,10 @@ typedef struct {
                            selinv_streams assignment as lanes of one stream,
                            each launch taking the next operation of every
                            lane that has one of its kind ready (one grid, no
-                           library streams, also inside stream captures);
-                           0 (default): one stream per subtree */
+                           library streams, also inside stream captures;
+                           complex-symmetric pencils, the Hermitian path
+                           keeps its streams); 0 (default): one stream per
+                           subtree */
   double reserved1[2];
 } pxs_options;
 
