@@ -260,9 +260,19 @@ def chain_leg(reps=200):
     eager_us = timed(lambda: B.density_matrix(a, H, S, lattice.BETA_300K, dE, mu, P, nsets=2, L=L, work=W), reps // 4)
     noalloc_us = timed(lambda: B.density_matrix_noalloc(a, H, S, lattice.BETA_300K, dE, mu, P, nsets=2, L=L),
                        reps // 4)
+    # the same plan with the subtrees on streams instead of fused lanes
+    # (the analysis fuses them by default for this tree of small supernodes);
+    # timed last: eager calls right after many replays of a large graph were
+    # measured up to 2x slower for a while
+    a_st = B.Analysis.from_system(s, fused_lanes=-1).bind()
+    plan_st = B.Plan(a_st, H, S, P, nsets=2)
+    plan_streams_us = timed(lambda: plan_st.run_device(sh_d, wt_d), reps)
+    del plan_st
     return {"workload": WORKLOADS["chain"]["desc"], "graph_plan_us_per_density_matrix": round(plan_us, 1),
             "graph_plan_pole_solves_per_s": round(P / (plan_us * 1e-6), 1),
             "graph_plan_host_table_us_per_density_matrix": round(plan_host_us, 1),
+            "fused_lanes": a.info["fused_lanes"],
+            "graph_plan_streams_us_per_density_matrix": round(plan_streams_us, 1),
             "eager_us_per_density_matrix": round(eager_us, 1),
             "noalloc_us_per_density_matrix": round(noalloc_us, 1), "replays": reps}
 
@@ -547,9 +557,9 @@ def main():
     ap.add_argument("--leaf-cols", type=int, default=0)
     ap.add_argument("--selinv-streams", type=int, default=0)
     ap.add_argument("--selinv-chunk", type=int, default=0)
-    ap.add_argument("--selinv-fused", type=int, default=-1,
-                    help="1: SelInv subtree lanes fused on one stream, 0: one stream per subtree "
-                         "(default: the tuned choice)")
+    ap.add_argument("--fused-lanes", type=int, default=None,
+                    help="1: subtree lanes fused on one stream, -1: one stream per subtree, "
+                         "0: by structure (default: the analysis' own choice)")
     ap.add_argument("--sep-cols", type=int, default=-1,
                     help="max columns of a separator supernode (0: no cut; default: the tuned value)")
     ap.add_argument("--hbm-budget-gib", type=float, default=270.0,
@@ -659,8 +669,8 @@ def main():
     else:
         from paper_1405_0194_amd import tune
         a = tune.tuned_analysis(s, lattice.CONFIG_POLES[cfg])
-    if args.selinv_fused >= 0 and a.options.get("selinv_fused", 0) != args.selinv_fused:
-        a = B.Analysis.from_system(s, **{**a.options, "selinv_fused": args.selinv_fused})
+    if args.fused_lanes is not None and a.options.get("fused_lanes", 0) != args.fused_lanes:
+        a = B.Analysis.from_system(s, **{**a.options, "fused_lanes": args.fused_lanes})
     # SelInv works on shift chunks when the whole batch's workspace would not
     # fit beside the factors (the cubic bulk: 201 GB of factors for 80 shifts)
     if not args.selinv_chunk:
@@ -769,6 +779,14 @@ def main():
     avg_ms = kms / max(klaunch, 1)
     achieved = (kwork / max(klaunch, 1)) / (avg_ms / 1e3) / 1e12 if klaunch else 0.0
     traffic = measured_traffic(args.profile_kernel, args.workload)
+    # device-level rate of each phase: its exact flops over its wall time in
+    # the phase-breakdown step (independent of how the launches overlap)
+    phase_rates = {}
+    for name, fl, key in (("factor", a.info["flops_factor"], "assemble_factor_ms"),
+                          ("selinv", a.info["flops_selinv"], "selinv_ms")):
+        if phases.get(key):
+            t = fl * P / (phases[key] / 1e3) / 1e12
+            phase_rates[name] = {"tflops": round(t, 3), "frac": round(t / PEAK_FP64_TFLOPS, 4)}
     lat_sorted = sorted(lat)
     res = {
         "metric": "pole-solves/sec (LDL^T+SelInv), FP64 MFMA %, p50/p99 request latency",
@@ -791,6 +809,7 @@ def main():
         "latency_s": {"p50": round(float(np.percentile(lat_sorted, 50)), 4),
                       "p99": round(float(np.percentile(lat_sorted, 99)), 4)},
         "phases_ms": {k: round(v, 2) for k, v in phases.items()},
+        "phase_rates": phase_rates,
         "hbm_GBps": hbm,
         "cold_s": {"analyze": round(t_an, 3), "bind": round(t_bind, 3),
                    "first_density_matrix": round(first_step, 3) if first_step is not None else None},

@@ -94,14 +94,19 @@ typedef struct {
                            at most this many columns, each a supernode whose
                            rows below are the union of its own columns'
                            structures (fewer stored zeros); 0: no cut */
-  int32_t selinv_fused; /* 1: selected inversion runs the subtrees of the
-                           selinv_streams assignment as lanes of one stream,
-                           each launch taking the next operation of every
-                           lane that has one of its kind ready (one grid, no
+  int32_t fused_lanes; /* 1: the factorization's panel work and selected
+                           inversion run the subtrees of the selinv_streams
+                           assignment as lanes of the caller's stream, each
+                           launch taking the next operation of every lane
+                           that has one of its kind ready (one grid, no
                            library streams, also inside stream captures;
-                           complex-symmetric pencils, the Hermitian path
-                           keeps its streams); 0 (default): one stream per
-                           subtree */
+                           fewer, fuller launches: about half the time of a
+                           small-supernode system such as a 1D chain);
+                           -1: one stream per subtree; 0 (default): lanes
+                           when the average supernode holds under 1e8 flops
+                           per shift, else streams.  Complex-symmetric
+                           pencils and inertia counts; the Hermitian path
+                           keeps its streams */
   double reserved1[2];
 } pxs_options;
 
@@ -138,6 +143,10 @@ typedef struct {
                                   a by-product of the blocked algorithm) and
                                   [7] are 0.  [1]+[3]+[6] = flops_factor / 8,
                                   [0]+[2]+[4] = flops_selinv / 8. */
+  int64_t fused_lanes;         /* 1 if the subtree lanes run fused on one
+                                  stream (pxs_options.fused_lanes), else 0 */
+  int64_t sel_lanes;           /* subtree streams or lanes (at most
+                                  selinv_streams; 1: everything in order) */
 } pxs_syminfo;
 
 /* ---------------------------------------------------------------------- */

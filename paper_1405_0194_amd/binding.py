@@ -32,7 +32,7 @@ class c64(C.Structure):
 class Options(C.Structure):
     _fields_ = [("ordering", C.c_int32), ("leaf_cols", C.c_int32), ("panel_width", C.c_int32),
                 ("selinv_chunk", C.c_int32), ("pivot_tol", C.c_double), ("tile_rows", C.c_int32),
-                ("selinv_streams", C.c_int32), ("sep_cols", C.c_int32), ("selinv_fused", C.c_int32),
+                ("selinv_streams", C.c_int32), ("sep_cols", C.c_int32), ("fused_lanes", C.c_int32),
                 ("reserved1", C.c_double * 2)]
 
 
@@ -44,7 +44,7 @@ class SymInfo(C.Structure):
                 ("gather_per_shift", C.c_int64), ("selinv_chunk", C.c_int64),
                 ("map_bytes", C.c_int64), ("max_front", C.c_int64),
                 ("flops_factor", C.c_double), ("flops_selinv", C.c_double),
-                ("macs_exact", C.c_double * 8)]
+                ("macs_exact", C.c_double * 8), ("fused_lanes", C.c_int64), ("sel_lanes", C.c_int64)]
 
 
 _P = C.c_void_p
@@ -179,7 +179,7 @@ class Analysis:
 
     def __init__(self, n, colptr, rowind, blkptr=None, coords=None, ordering=0, leaf_cols=0,
                  panel_width=0, pivot_tol=0.0, selinv_chunk=0, tile_rows=0, selinv_streams=0, sep_cols=0,
-                 selinv_fused=0):
+                 fused_lanes=0):
         lib = load()
         self._lib = lib
         self.n = int(n)
@@ -187,9 +187,9 @@ class Analysis:
         rowind = np.ascontiguousarray(rowind, dtype=np.int32)
         self.options = dict(ordering=ordering, leaf_cols=leaf_cols, panel_width=panel_width,
                             pivot_tol=pivot_tol, selinv_chunk=selinv_chunk, tile_rows=tile_rows,
-                            selinv_streams=selinv_streams, sep_cols=sep_cols, selinv_fused=selinv_fused)
+                            selinv_streams=selinv_streams, sep_cols=sep_cols, fused_lanes=fused_lanes)
         opt = Options(ordering, leaf_cols, panel_width, selinv_chunk, pivot_tol, tile_rows, selinv_streams,
-                      sep_cols, selinv_fused)
+                      sep_cols, fused_lanes)
         h = _P()
         nblk = 0
         bp = None

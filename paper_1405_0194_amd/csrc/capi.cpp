@@ -126,8 +126,8 @@ pxs_status pxs_analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, 
     if (opt->tile_rows) o.tile_rows = opt->tile_rows;
     if (opt->selinv_streams < 0 || opt->selinv_streams > 8) return PXS_EINVAL;
     if (opt->selinv_streams) o.selinv_streams = opt->selinv_streams;
-    if (opt->selinv_fused != 0 && opt->selinv_fused != 1) return PXS_EINVAL;
-    o.selinv_fused = opt->selinv_fused;
+    if (opt->fused_lanes < -1 || opt->fused_lanes > 1) return PXS_EINVAL;
+    o.fused_lanes = opt->fused_lanes;
     if (o.ordering != 0 && o.ordering != 1) return PXS_EINVAL;
     if (o.panel_width > 64) return PXS_EINVAL;
   }
@@ -179,6 +179,8 @@ pxs_status pxs_symbolic_info(pxs_symbolic sym, pxs_syminfo* info) {
     info->macs_exact[0] += m.sfinal;
   }
   for (double u : S.xm_update) info->macs_exact[pxs::KC_UPDATE] += u;
+  info->fused_lanes = S.fused_lanes;
+  info->sel_lanes = S.sel_nstreams;
   return PXS_OK;
 }
 

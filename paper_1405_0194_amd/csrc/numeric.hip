@@ -1534,10 +1534,137 @@ int run_factor_kernels(const Symbolic& S, const double* H, const double* Sv, int
   // its scatters in the same order and the factors are bit-identical whether
   // the subtree streams are used or not.  Inside a stream capture, or with
   // one subtree stream, everything runs on the caller's stream.
+  int err = 0;
+  if (S.fused_lanes && NS > 1) {
+    // fused lanes (see run_selinv_lanes; no library streams or events, so
+    // also on the in-order paths): the panel operations of each lane
+    // (the sel_stream subtrees, supernodes in fac_order) and one more lane of
+    // the ancestor scatters in fac_order, all on the caller's stream; a
+    // launch takes the next operation of every ready lane of one kind.  The
+    // first panel operation of J waits for the scatter of fac_child[J] (and
+    // so for every scatter before it), a scatter for the last panel
+    // operation of its supernode; scatters are never fused with each other.
+    enum : int32_t { FK_INT, FK_DIAG, FK_TRSM, FK_UPD };
+    struct FOp {
+      int32_t kind, J;
+      bool first, last;
+      GroupItem it;
+      double work, bytes, stored;
+    };
+    if (NS > MAX_LANES) return (int)hipErrorInvalidValue;
+    std::vector<std::vector<FOp>> lane(NS + 1);   // lane NS: the scatters
+    for (int J : S.fac_order) {
+      if (pfirst[J] < 0) continue;
+      std::vector<FOp>& ops = lane[S.sel_stream[J]];
+      const size_t n0 = ops.size();
+      auto add = [&](std::vector<FOp>& v, int32_t kind, const PanelK& k, int64_t tiles, double w, double b,
+                     double s) {
+        FOp o;
+        o.kind = kind;
+        o.J = J;
+        o.first = &v == &ops && v.size() == n0;
+        o.last = false;
+        o.it.c = c;
+        o.it.p = k;
+        o.it.start = 0;
+        o.it.tiles = (int32_t)tiles;
+        o.it.nsh = nshift;
+        o.work = w;
+        o.bytes = b;
+        o.stored = s;
+        v.push_back(o);
+      };
+      for (int ip = pfirst[J]; ip <= plast[J]; ++ip) {
+        const PanelK k = panel_args(S, S.panels[ip]);
+        const PanelMacs& xm = S.xm_panel[ip];
+        if (k.p0 > 0) {
+          const int nrows = k.ld - k.p0;
+          add(ops, FK_INT, k, (nrows + TR - 1) / TR, fm * nshift * xm.intu,
+              eb * nshift * ((double)nrows * k.p0 + 2.0 * nrows * k.wp),
+              fm * nshift * ((double)nrows * k.wp - 0.5 * k.wp * (k.wp - 1)) * k.p0);
+        }
+        add(ops, FK_DIAG, k, 1, fm * nshift * xm.diag, eb * nshift * (double)k.wp * (k.wp + 1),
+            fm * nshift * (double)k.wp * k.wp * k.wp / 3.0);
+        if (k.nb > 0)
+          add(ops, FK_TRSM, k, (k.nb + TR - 1) / TR, fm * nshift * xm.trsm,
+              eb * nshift * (2.0 * k.nb * k.wp + 0.5 * k.wp * (k.wp + 1)),
+              fm * nshift * (double)k.nb * k.wp * (k.wp + 1) / 2.0);
+      }
+      ops.back().last = true;
+      if (S.sparent[J] >= 0) add(lane[NS], FK_UPD, panel_args(S, S.panels[plast[J]]), 0, 0.0, 0.0, 0.0);
+    }
+    std::vector<int64_t> pdone(ns, -1), sdone(ns, -1);   // launch of J's last panel op / scatter
+    std::vector<size_t> pos(NS + 1, 0);
+    int64_t nl = 0;
+    auto ready = [&](int q) {
+      if (pos[q] >= lane[q].size()) return false;
+      const FOp& o = lane[q][pos[q]];
+      if (q == NS) return pdone[o.J] >= 0 && pdone[o.J] < nl;
+      if (!o.first) return true;
+      const int ch = S.fac_child[o.J];
+      return ch < 0 || (sdone[ch] >= 0 && sdone[ch] < nl);
+    };
+    for (;;) {
+      int lead = -1;
+      size_t most = 0;
+      for (int q = 0; q <= NS; ++q) {
+        if (!ready(q)) continue;
+        const size_t left = lane[q].size() - pos[q];
+        if (left > most) {
+          most = left;
+          lead = q;
+        }
+      }
+      if (lead < 0) break;
+      const int32_t kind = lane[lead][pos[lead]].kind;
+      if (kind == FK_UPD) {
+        const FOp& o = lane[NS][pos[NS]];
+        if ((err = scatter(S.panels[plast[o.J]], st))) return err;
+        sdone[o.J] = nl++;
+        ++pos[NS];
+        continue;
+      }
+      LaneGroup grp;
+      grp.n = 0;
+      int64_t start = 0;
+      double w = 0.0, b = 0.0, s = 0.0;
+      for (int q = 0; q < NS; ++q) {
+        if (!ready(q) || lane[q][pos[q]].kind != kind) continue;
+        const FOp& o = lane[q][pos[q]];
+        GroupItem it = o.it;
+        it.start = start;
+        start += (int64_t)it.tiles * it.nsh;
+        grp.it[grp.n++] = it;
+        w += o.work;
+        b += o.bytes;
+        s += o.stored;
+        if (o.last) pdone[o.J] = nl;
+        ++pos[q];
+      }
+      if (start > (int64_t)INT32_MAX) return (int)hipErrorInvalidConfiguration;
+      const dim3 grid((unsigned)start);
+      if (kind == FK_INT) {
+        ProfScope ps(KC_UPDATE, st, w, b, s);
+        if (TR == 64) hipLaunchKernelGGL((k_int_update<CPLX, 64, LaneGroup>), grid, dim3(NT), 0, st, grp);
+        else hipLaunchKernelGGL((k_int_update<CPLX, 128, LaneGroup>), grid, dim3(NT), 0, st, grp);
+      } else if (kind == FK_DIAG) {
+        ProfScope ps(KC_DIAG, st, w, b, s);
+        hipLaunchKernelGGL((k_diag<CPLX, LaneGroup>), grid, dim3(NTD), 0, st, grp);
+      } else {
+        ProfScope ps(KC_TRSM, st, w, b, s);
+        if (TR == 64) hipLaunchKernelGGL((k_trsm<CPLX, 64, LaneGroup>), grid, dim3(NT), 0, st, grp);
+        else hipLaunchKernelGGL((k_trsm<CPLX, 128, LaneGroup>), grid, dim3(NT), 0, st, grp);
+      }
+      PXS_CHECK_LAUNCH();
+      ++nl;
+    }
+    for (int q = 0; q <= NS; ++q)
+      if (pos[q] != lane[q].size()) return (int)hipErrorUnknown;   // unreachable: some lane is always ready
+    return 0;
+  }
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   hipError_t he = hipStreamIsCapturing(st, &cap);
   if (he != hipSuccess) return (int)he;
-  int err = 0;
   if (cap != hipStreamCaptureStatusNone || NS <= 1 || inorder) {
     for (int J : S.fac_order) {
       if (pfirst[J] < 0) continue;
@@ -1639,7 +1766,7 @@ int selinv_event_count(const Symbolic& S) { return S.nsuper + S.sel_nstreams + 1
 
 namespace {
 
-// Selected inversion with the subtree lanes fused (sel_fused).  The
+// Selected inversion with the subtree lanes fused (fused_lanes).  The
 // supernodes keep the lanes of the stream assignment (sel_stream) and each
 // lane its own workspace regions, as on separate streams; the operations of
 // a lane (per supernode from the root down: the Z_CC gather, then per panel
@@ -1813,7 +1940,7 @@ int run_selinv_lanes(const Symbolic& S, int nshift, void* L, void* work, hipStre
 
 int run_selinv(const Symbolic& S, int nshift, void* L, void* work, hipStream_t st,
                hipEvent_t* events, bool inorder) {
-  if (S.sel_fused && !inorder && S.sel_nstreams > 1) return run_selinv_lanes(S, nshift, L, work, st);
+  if (S.fused_lanes && !inorder && S.sel_nstreams > 1) return run_selinv_lanes(S, nshift, L, work, st);
   // inside a stream capture everything runs on the capturing stream: the
   // subtree streams are used by eager runs only
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;

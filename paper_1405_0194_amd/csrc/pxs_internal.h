@@ -91,7 +91,7 @@ struct Symbolic {
   // when they are on different streams.  Each stream has its own per-shift
   // region (work_per_shift) and dense Z_CC region (gather_bytes[s] per shift).
   int32_t sel_nstreams = 1;
-  int32_t sel_fused = 0;   // run the sel_stream lanes fused on one stream
+  int32_t fused_lanes = 0;   // factor panel work and SelInv: the sel_stream lanes fused on one stream
   std::vector<int32_t> sel_stream;
   std::vector<int64_t> gather_bytes;
   std::vector<uint8_t> cross_child;  // J has a child on another stream
@@ -113,10 +113,14 @@ struct AnalyzeOptions {
   int ordering = 0;
   int leaf_cols = 128;
   int sep_cols = 0;        // 0: every separator is one supernode
-  int selinv_fused = 0;    // 1: SelInv lanes fused on one stream
+  int fused_lanes = 0;    // 1: subtree lanes fused on one stream (factor and SelInv), -1: never, 0: by structure
   int panel_width = 64;
   double pivot_tol = 1e-14;
 };
+
+// Automatic lane fusion (AnalyzeOptions.fused_lanes = 0) below this many
+// flops per supernode and shift.
+constexpr double FUSE_FLOPS_PER_SUPER = 1e8;
 
 // Returns 0 on success, -1 on invalid input (msg set).
 int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nblk,

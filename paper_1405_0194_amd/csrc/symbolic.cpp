@@ -716,7 +716,18 @@ int analyze(int32_t n, const int64_t* colptr, const int32_t* rowind, int32_t nbl
     }
   }
   S.selinv_chunk = std::max(0, opt.selinv_chunk);
-  S.sel_fused = opt.selinv_fused ? 1 : 0;
+  // Subtree lanes fused on one stream: on request, or, by default, when the
+  // average supernode carries under FUSE_FLOPS_PER_SUPER flops per shift --
+  // trees of many small supernodes (1D chains), whose launches are short
+  // and latency-bound: one fused grid per step halves their density-matrix
+  // time, while systems of a few large supernodes run at the same speed or
+  // 1-3% slower (measured over 64 chain, sheet and bulk systems)
+  if (opt.fused_lanes != 0) {
+    S.fused_lanes = opt.fused_lanes > 0 ? 1 : 0;
+  } else {
+    const double per = (S.flops_factor + S.flops_selinv) / std::max(1, ns);
+    S.fused_lanes = per < FUSE_FLOPS_PER_SUPER ? 1 : 0;
+  }
   S.tile_rows = (opt.tile_rows == 128) ? 128 : 64;
   return 0;
 }

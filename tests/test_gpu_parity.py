@@ -142,8 +142,9 @@ def test_inertia_counts_match_eigenvalues(torch_cuda):
     ("chain", 301, 3, 2.0, dict(panel_width=7, leaf_cols=33, tile_rows=128)),
     ("cubic", (6, 5, 5), 13, 2.0, dict(sep_cols=130)),
     ("cubic", (5, 5, 6), 5, 2.0, dict(sep_cols=20, panel_width=16, selinv_chunk=9)),
-    ("cubic", (6, 5, 5), 13, 2.0, dict(selinv_fused=1)),
-    ("honeycomb", (8, 7), 13, 3.0, dict(selinv_fused=1, selinv_streams=8, selinv_chunk=11, tile_rows=128)),
+    ("cubic", (6, 5, 5), 13, 2.0, dict(fused_lanes=1)),
+    ("chain", 301, 3, 2.0, dict(panel_width=7, leaf_cols=33, fused_lanes=-1)),
+    ("honeycomb", (8, 7), 13, 3.0, dict(fused_lanes=1, selinv_streams=8, selinv_chunk=11, tile_rows=128)),
 ])
 def test_lattice_parity_several_tiles(torch_cuda, kind, dims, orb, cut, akw):
     torch = torch_cuda
@@ -372,7 +373,7 @@ def test_full_size_cubic_configuration(torch_cuda):
     _full_size_check(torch_cuda, 2)
 
 
-@pytest.mark.parametrize("fused", [0, 1])
+@pytest.mark.parametrize("fused", [-1, 1])
 def test_graph_plan_replays_match_eager(torch_cuda, fused):
     """The captured graph replayed several times (with eager library work and
     synchronisations in between, new pole tables and new H values) gives the
@@ -381,7 +382,7 @@ def test_graph_plan_replays_match_eager(torch_cuda, fused):
     torch = torch_cuda
     from paper_1405_0194_amd import binding as B
     s = lattice.make_system("honeycomb", (6, 5), 13, 3.0, 31)
-    a = B.Analysis.from_system(s, selinv_fused=fused)
+    a = B.Analysis.from_system(s, fused_lanes=fused)
     H = _dev(torch, s.hval)
     S = _dev(torch, s.sval)
     P = 20
@@ -419,9 +420,9 @@ def test_results_do_not_depend_on_the_subtree_streams(torch_cuda):
     sh, wt = B.poles(BETA, 1.0, 0.0, P, 2)
     eps = np.array([-0.3, -0.01, 0.0, 0.2])
     ref = None
-    for ns, fused in ((1, 0), (2, 0), (4, 0), (8, 0), (4, 1), (8, 1)):
+    for ns, fused in ((1, -1), (2, -1), (4, -1), (8, -1), (4, 1), (8, 1)):
         say("case: subtree streams", ns, "fused lanes", fused, "N", s.n)
-        a = B.Analysis.from_system(s, selinv_streams=ns, selinv_fused=fused)
+        a = B.Analysis.from_system(s, selinv_streams=ns, fused_lanes=fused)
         f = B.Factorization(a, H, S, sh)
         d = f.diag(5).cpu().numpy().copy()
         f.selinv()

@@ -307,16 +307,23 @@ def test_exact_macs_per_kernel_class_atom_blocks():
     assert np.allclose(np.array(a.info["macs_exact"]), want, rtol=1e-12, atol=0)
 
 
-def test_fused_selinv_option_values():
-    """selinv_fused takes 0 or 1; it leaves the structure, the sizes and the
-    workspace of the analysis unchanged (the fused lanes use the regions of
-    the subtree streams)."""
-    s = lattice.make_system("honeycomb", (6, 6), 4, 3.0, 3)
+def test_fused_lanes_option_values():
+    """fused_lanes takes -1, 0 or 1; it leaves the structure, the sizes and
+    the workspace of the analysis unchanged (fused lanes use the regions of
+    the subtree streams).  By default (0) the lanes are fused for trees of
+    small supernodes (a 1D chain) and not for large ones (a 13-orbital
+    sheet); -1 and 1 force either."""
+    s = lattice.make_system("honeycomb", (6, 6), 13, 3.0, 3)
     a0 = B.Analysis.from_system(s)
-    a1 = B.Analysis.from_system(s, selinv_fused=1)
-    for k in ("nnz_L", "nsuper", "npanel", "bytes_per_shift", "work_bytes", "gather_per_shift"):
+    a1 = B.Analysis.from_system(s, fused_lanes=1)
+    for k in ("nnz_L", "nsuper", "npanel", "bytes_per_shift", "work_bytes", "gather_per_shift", "sel_lanes"):
         assert a0.info[k] == a1.info[k], k
     assert a0.workspace_size(20) == a1.workspace_size(20)
-    for bad in (-1, 2):
+    assert a0.info["fused_lanes"] == 0 and a1.info["fused_lanes"] == 1
+    assert a0.info["sel_lanes"] > 1
+    c = lattice.config_system(0)
+    assert B.Analysis.from_system(c).info["fused_lanes"] == 1
+    assert B.Analysis.from_system(c, fused_lanes=-1).info["fused_lanes"] == 0
+    for bad in (-2, 2):
         with pytest.raises(B.PxsError):
-            B.Analysis.from_system(s, selinv_fused=bad)
+            B.Analysis.from_system(s, fused_lanes=bad)
