@@ -230,10 +230,11 @@ def chain_leg(reps=200):
     import torch
     from paper_1405_0194_amd import binding as B
     from paper_1405_0194_amd import lattice
+    from paper_1405_0194_amd import tune
     s = lattice.config_system(0)
     P, mu = lattice.CONFIG_POLES[0], 0.0
     dE = 1.0 + abs(mu)
-    a = B.Analysis.from_system(s).bind()
+    a = tune.tuned_analysis(s, P).bind()
     H = torch.from_numpy(s.hval).cuda()
     S = torch.from_numpy(s.sval).cuda()
     plan = B.Plan(a, H, S, P, nsets=2)
@@ -264,7 +265,7 @@ def chain_leg(reps=200):
     # (the analysis fuses them by default for this tree of small supernodes);
     # timed last: eager calls right after many replays of a large graph were
     # measured up to 2x slower for a while
-    a_st = B.Analysis.from_system(s, fused_lanes=-1).bind()
+    a_st = B.Analysis.from_system(s, **{**a.options, "fused_lanes": -1}).bind()
     plan_st = B.Plan(a_st, H, S, P, nsets=2)
     plan_streams_us = timed(lambda: plan_st.run_device(sh_d, wt_d), reps)
     del plan_st
