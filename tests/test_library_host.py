@@ -327,3 +327,13 @@ def test_fused_lanes_option_values():
     for bad in (-2, 2):
         with pytest.raises(B.PxsError):
             B.Analysis.from_system(s, fused_lanes=bad)
+
+
+def test_lane_fusion_rule_over_the_batch_mix():
+    """The structural default fuses the subtree lanes of every 1D chain of
+    the 64-system mix (many supernodes of a few hundred columns, latency
+    bound) and of no 2D sheet or 3D bulk system (a few large supernodes)."""
+    for s, P in lattice.batch_systems():
+        a = B.Analysis.from_system(s)
+        per = (a.info["flops_factor"] + a.info["flops_selinv"]) / a.info["nsuper"]
+        assert a.info["fused_lanes"] == (1 if s.kind == "chain" else 0), (s.kind, s.n, per)
