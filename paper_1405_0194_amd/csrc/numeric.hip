@@ -148,7 +148,25 @@ struct NoScale {};
 
 // SCALE: A[m][k] is multiplied by the chunk's d_k (staged with the chunk)
 // as it is read for the matrix cores.
-template <bool CPLX, int NTILE, bool SCALE = false>
+// Row of the 16-row block a of wave w: blocks in order (SWZ = false), or,
+// for the 64-row tiles of products with a triangular A operand, the waves of
+// the first wave row taking blocks {0, 3} and of the second {1, 2}, so that
+// both rows skip equally many all-zero blocks.
+template <int NTILE, bool SWZ>
+__device__ __forceinline__ int block_row(int w, int a) {
+  using G = Geo<NTILE>;
+  if constexpr (SWZ) {
+    static_assert(G::BM == 2 && G::WM == 2, "block swizzle needs 2 x 2 waves of 2 blocks");
+    const int wr = w / G::WN;
+    return 16 * (a == 0 ? wr : 3 - wr);
+  } else {
+    return (w / G::WN) * (G::BM * 16) + a * 16;
+  }
+}
+
+// MASK >= 0: only the m-blocks a with bit a set are multiplied (the others
+// are zero in this chunk's A operand).
+template <bool CPLX, int NTILE, bool SCALE = false, int MASK = -1, bool SWZ = false>
 __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CPLX, NTILE>& s) {
   using G = Geo<NTILE>;
   // the compiler's single-wave small-GEMM schedule (interleaves the LDS
@@ -156,7 +174,7 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CP
   __builtin_amdgcn_iglp_opt(1);
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int wm = (w / G::WN) * (G::BM * 16), wn = (w % G::WN) * 32;
+  const int wn = (w % G::WN) * 32;
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int ks = 0; ks < KC / 4; ++ks) {
@@ -164,8 +182,9 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CP
     double ar[G::BM], ai[G::BM], br[G::BN], bi[G::BN];
 #pragma unroll
     for (int t = 0; t < G::BM; ++t) {
-      ar[t] = s.a_re[k][wm + t * 16 + li];
-      if (CPLX) ai[t] = s.a_im[k][wm + t * 16 + li];
+      if (MASK >= 0 && !((MASK >> t) & 1)) continue;
+      ar[t] = s.a_re[k][block_row<NTILE, SWZ>(w, t) + li];
+      if (CPLX) ai[t] = s.a_im[k][block_row<NTILE, SWZ>(w, t) + li];
     }
     if (SCALE) {
       const double dr = s.d_re[k];
@@ -173,13 +192,15 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CP
         const double di = s.d_im[k];
 #pragma unroll
         for (int t = 0; t < G::BM; ++t) {
+          if (MASK >= 0 && !((MASK >> t) & 1)) continue;
           const cplx v = cmul(cplx{dr, di}, cplx{ar[t], ai[t]});
           ar[t] = v.re;
           ai[t] = v.im;
         }
       } else {
 #pragma unroll
-        for (int t = 0; t < G::BM; ++t) ar[t] *= dr;
+        for (int t = 0; t < G::BM; ++t)
+          if (!(MASK >= 0 && !((MASK >> t) & 1))) ar[t] *= dr;
       }
     }
 #pragma unroll
@@ -191,6 +212,7 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CP
     for (int a = 0; a < G::BM; ++a)
 #pragma unroll
       for (int b = 0; b < G::BN; ++b) {
+        if (MASK >= 0 && !((MASK >> a) & 1)) continue;
         acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc.re[a][b], 0, 0, 0);
         if (CPLX) {
           acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], acc.re[a][b], 0, 0, 1);   // -ai bi
@@ -202,19 +224,19 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CP
 }
 
 // Visits every accumulator element as (m, n, value).
-template <bool CPLX, int NTILE, class F>
+template <bool CPLX, int NTILE, bool SWZ = false, class F>
 __device__ __forceinline__ void acc_foreach(const Acc<CPLX, NTILE>& acc, F f) {
   using G = Geo<NTILE>;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int wm = (w / G::WN) * (G::BM * 16), wn = (w % G::WN) * 32;
+  const int wn = (w % G::WN) * 32;
 #pragma unroll
   for (int a = 0; a < G::BM; ++a)
 #pragma unroll
     for (int b = 0; b < G::BN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = wm + a * 16 + (lane >> 4) + 4 * r;
+        const int m = block_row<NTILE, SWZ>(w, a) + (lane >> 4) + 4 * r;
         const int n = wn + b * 16 + (lane & 15);
         cplx v{acc.re[a][b][r], CPLX ? acc.im[a][b][r] : 0.0};
         f(m, n, v);
@@ -383,9 +405,42 @@ struct Stage2 {
 // order per chunk.  gd(k), unless NoScale, returns a factor d_k applied to
 // column k of A on its way to the matrix cores (one load per k and chunk
 // instead of one per element); it must accept any k of the last chunk.
-template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF, class GD = NoScale>
+// Which m-blocks of the wave take part in a chunk: all (AllLive), or, for a
+// triangular A operand on a 64-row tile (TriLive; the swizzled block rows),
+// those whose rows meet the chunk's k range in the nonzero triangle.
+struct AllLive {
+  static constexpr bool kAll = true, kSwz = false;
+  __device__ int operator()(int) const { return 3; }
+};
+template <bool LOWER>   // LOWER: A[m][k] = 0 for k > m; else A[m][k] = 0 for k < m
+struct TriLive {
+  static constexpr bool kAll = false, kSwz = true;
+  __device__ int operator()(int k0) const {
+    static_assert(KC == 16, "a chunk spans one 16-row block");
+    const int wr = (threadIdx.x >> 6) / Geo<64>::WN;
+    const int c = k0 / KC;
+    const int mb0 = wr, mb1 = 3 - wr;
+    const bool l0 = LOWER ? c <= mb0 : c >= mb0;
+    const bool l1 = LOWER ? c <= mb1 : c >= mb1;
+    return __builtin_amdgcn_readfirstlane((l0 ? 1 : 0) | (l1 ? 2 : 0));
+  }
+};
+
+template <bool CPLX, int NTILE, bool SC, class LV>
+__device__ __forceinline__ void run_chunk(Acc<CPLX, NTILE>& acc, const Stage<CPLX, NTILE>& st, LV lv, int k0) {
+  if constexpr (LV::kAll) {
+    mfma_chunk<CPLX, NTILE, SC>(acc, st);
+  } else {
+    const int m = lv(k0);
+    if (m == 3) mfma_chunk<CPLX, NTILE, SC, 3, LV::kSwz>(acc, st);
+    else if (m == 2) mfma_chunk<CPLX, NTILE, SC, 2, LV::kSwz>(acc, st);
+    else if (m == 1) mfma_chunk<CPLX, NTILE, SC, 1, LV::kSwz>(acc, st);
+  }
+}
+
+template <bool CPLX, int NTILE, bool AFAST, class GA, class GB, class BF, class GD = NoScale, class LV = AllLive>
 __device__ __forceinline__ void gemm_pipe(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NTILE>& s, int kb, int ke,
-                                          GA ga, GB gb, BF bfast, GD gd = GD()) {
+                                          GA ga, GB gb, BF bfast, GD gd = GD(), LV lv = LV()) {
   using G = Geo<NTILE>;
   constexpr bool SC = !std::is_same<GD, NoScale>::value;
   if (kb >= ke) return;
@@ -423,7 +478,7 @@ __device__ __forceinline__ void gemm_pipe(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NT
   dfetch(rd0, kat(2));
   __syncthreads();
   for (int c = 0; c < nc; c += 2) {
-    mfma_chunk<CPLX, NTILE, SC>(acc, s.buf[0]);
+    run_chunk<CPLX, NTILE, SC>(acc, s.buf[0], lv, kb + c * KC);
     commit<CPLX, 64, G::XA, AFAST>(&s.buf[1].a_re[0][0], &s.buf[1].a_im[0][0], ra1);
     commit_rt<CPLX, NTILE, G::XB>(&s.buf[1].b_re[0][0], &s.buf[1].b_im[0][0], rb1, fb1);
     dcommit(s.buf[1], rd1);
@@ -433,7 +488,7 @@ __device__ __forceinline__ void gemm_pipe(Acc<CPLX, NTILE>& acc, Stage2<CPLX, NT
     dfetch(rd1, kat(c + 3));
     __syncthreads();
     if (c + 1 >= nc) break;
-    mfma_chunk<CPLX, NTILE, SC>(acc, s.buf[1]);
+    run_chunk<CPLX, NTILE, SC>(acc, s.buf[1], lv, kb + (c + 1) * KC);
     commit<CPLX, 64, G::XA, AFAST>(&s.buf[0].a_re[0][0], &s.buf[0].a_im[0][0], ra0);
     commit_rt<CPLX, NTILE, G::XB>(&s.buf[0].b_re[0][0], &s.buf[0].b_im[0][0], rb0, fb0);
     dcommit(s.buf[0], rd0);
@@ -797,6 +852,9 @@ __global__ void PXS_LB(TN) k_trsm(Src src) {
   }
   Acc<CPLX, TN> acc;
   acc.zero();
+  // L^{-1} is lower triangular: on 64-row tiles the all-zero blocks of a
+  // chunk are not multiplied
+  using LV = std::conditional_t<TN == 64, TriLive<true>, AllLive>;
   gemm_pipe<CPLX, TN, false>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[c][k]: column k of the diagonal block
@@ -807,8 +865,8 @@ __global__ void PXS_LB(TN) k_trsm(Src src) {
         const int ig = i0 + n;
         return ld_or_zero<CPLX>(Ls, rbase + (int64_t)kg * p.ld + ig, kg < p.wp && ig < p.nb);
       },
-      RowsFast());
-  acc_foreach<CPLX, TN>(acc, [&](int m, int n, cplx v) {
+      RowsFast(), NoScale(), LV());
+  acc_foreach<CPLX, TN, LV::kSwz>(acc, [&](int m, int n, cplx v) {
     const int ig = i0 + n;
     if (m < p.wp && ig < p.nb) st_elem<CPLX>(Ls, rbase + (int64_t)m * p.ld + ig, cmul(v, dinv[m]));
   });
@@ -937,6 +995,8 @@ __global__ void PXS_LB(TN) k_lhat(Src src) {
   const int64_t rbase = dbase + p.wp;
   Acc<true, TN> acc;
   acc.zero();
+  // A[m][k] = L^{-1}[k][m] vanishes for k < m (see k_trsm)
+  using LV = std::conditional_t<TN == 64, TriLive<false>, AllLive>;
   gemm_pipe<true, TN, true>(
       acc, s, 0, p.wp,
       [&](int m, int kg) -> cplx {   // Linv[k][c]: column c of the diagonal block, rows k
@@ -947,8 +1007,8 @@ __global__ void PXS_LB(TN) k_lhat(Src src) {
         const int ig = i0 + n;
         return ld_or_zero<true>(Ls, rbase + (int64_t)kg * p.ld + ig, kg < p.wp && ig < p.nb);
       },
-      RowsFast());
-  acc_foreach<true, TN>(acc, [&](int m, int n, cplx v) {
+      RowsFast(), NoScale(), LV());
+  acc_foreach<true, TN, LV::kSwz>(acc, [&](int m, int n, cplx v) {
     const int ig = i0 + n;
     if (m < p.wp && ig < p.nb) st_elem<true>(W, (int64_t)m * p.nb + ig, v);
   });
