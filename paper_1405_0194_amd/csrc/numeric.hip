@@ -148,14 +148,15 @@ struct NoScale {};
 
 // SCALE: A[m][k] is multiplied by the chunk's d_k (staged with the chunk)
 // as it is read for the matrix cores.
-// Row of the 16-row block a of wave w: blocks in order (SWZ = false), or,
-// for the 64-row tiles of products with a triangular A operand, the waves of
-// the first wave row taking blocks {0, 3} and of the second {1, 2}, so that
-// both rows skip equally many all-zero blocks.
-template <int NTILE, bool SWZ>
+// Row of the 16-row block a (column of the 16-column block b) of wave w:
+// blocks in order, or, with bit 0 (bit 1) of SWZ on a 64 x 64 tile, the
+// first wave row (column) taking blocks {0, 3} and the second {1, 2}, so that
+// both skip equally many blocks of a triangle (products with a triangular
+// operand or a symmetric result).
+template <int NTILE, int SWZ>
 __device__ __forceinline__ int block_row(int w, int a) {
   using G = Geo<NTILE>;
-  if constexpr (SWZ) {
+  if constexpr ((SWZ & 1) != 0) {
     static_assert(G::BM == 2 && G::WM == 2, "block swizzle needs 2 x 2 waves of 2 blocks");
     const int wr = w / G::WN;
     return 16 * (a == 0 ? wr : 3 - wr);
@@ -163,26 +164,41 @@ __device__ __forceinline__ int block_row(int w, int a) {
     return (w / G::WN) * (G::BM * 16) + a * 16;
   }
 }
+template <int NTILE, int SWZ>
+__device__ __forceinline__ int block_col(int w, int b) {
+  using G = Geo<NTILE>;
+  if constexpr ((SWZ & 2) != 0) {
+    static_assert(G::BN == 2 && G::WN == 2, "block swizzle needs 2 x 2 waves of 2 blocks");
+    const int wc = w % G::WN;
+    return 16 * (b == 0 ? wc : 3 - wc);
+  } else {
+    return (w % G::WN) * 32 + b * 16;
+  }
+}
 
-// MASK >= 0: only the m-blocks a with bit a set are multiplied (the others
-// are zero in this chunk's A operand).
-template <bool CPLX, int NTILE, bool SCALE = false, int MASK = -1, bool SWZ = false>
+// MASK >= 0: only the block pairs (a, b) with bit 2a + b set are multiplied
+// (the others are zero in this chunk, or not needed).
+template <bool CPLX, int NTILE, bool SCALE = false, int MASK = -1, int SWZ = 0>
 __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CPLX, NTILE>& s) {
   using G = Geo<NTILE>;
   // the compiler's single-wave small-GEMM schedule (interleaves the LDS
   // operand reads with the MFMAs): 1-2% over the default schedule
   __builtin_amdgcn_iglp_opt(1);
+  static_assert(MASK < 0 || (G::BM == 2 && G::BN == 2), "block masks need 2 x 2 blocks per wave");
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int wn = (w % G::WN) * 32;
   const int li = lane & 15, lk = lane >> 4;
+  // a row block is read if any of its pairs is live, a column block likewise
+  auto row_live = [](int t) { return MASK < 0 || ((MASK >> (2 * t)) & 3) != 0; };
+  auto col_live = [](int t) { return MASK < 0 || ((MASK >> t) & 5) != 0; };
+  auto live = [](int a, int b) { return MASK < 0 || ((MASK >> (2 * a + b)) & 1) != 0; };
 #pragma unroll
   for (int ks = 0; ks < KC / 4; ++ks) {
     const int k = ks * 4 + lk;
     double ar[G::BM], ai[G::BM], br[G::BN], bi[G::BN];
 #pragma unroll
     for (int t = 0; t < G::BM; ++t) {
-      if (MASK >= 0 && !((MASK >> t) & 1)) continue;
+      if (!row_live(t)) continue;
       ar[t] = s.a_re[k][block_row<NTILE, SWZ>(w, t) + li];
       if (CPLX) ai[t] = s.a_im[k][block_row<NTILE, SWZ>(w, t) + li];
     }
@@ -192,7 +208,7 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CP
         const double di = s.d_im[k];
 #pragma unroll
         for (int t = 0; t < G::BM; ++t) {
-          if (MASK >= 0 && !((MASK >> t) & 1)) continue;
+          if (!row_live(t)) continue;
           const cplx v = cmul(cplx{dr, di}, cplx{ar[t], ai[t]});
           ar[t] = v.re;
           ai[t] = v.im;
@@ -200,19 +216,20 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CP
       } else {
 #pragma unroll
         for (int t = 0; t < G::BM; ++t)
-          if (!(MASK >= 0 && !((MASK >> t) & 1))) ar[t] *= dr;
+          if (row_live(t)) ar[t] *= dr;
       }
     }
 #pragma unroll
     for (int t = 0; t < G::BN; ++t) {
-      br[t] = s.b_re[k][wn + t * 16 + li];
-      if (CPLX) bi[t] = s.b_im[k][wn + t * 16 + li];
+      if (!col_live(t)) continue;
+      br[t] = s.b_re[k][block_col<NTILE, SWZ>(w, t) + li];
+      if (CPLX) bi[t] = s.b_im[k][block_col<NTILE, SWZ>(w, t) + li];
     }
 #pragma unroll
     for (int a = 0; a < G::BM; ++a)
 #pragma unroll
       for (int b = 0; b < G::BN; ++b) {
-        if (MASK >= 0 && !((MASK >> a) & 1)) continue;
+        if (!live(a, b)) continue;
         acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], acc.re[a][b], 0, 0, 0);
         if (CPLX) {
           acc.re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], acc.re[a][b], 0, 0, 1);   // -ai bi
@@ -224,12 +241,11 @@ __device__ __forceinline__ void mfma_chunk(Acc<CPLX, NTILE>& acc, const Stage<CP
 }
 
 // Visits every accumulator element as (m, n, value).
-template <bool CPLX, int NTILE, bool SWZ = false, class F>
+template <bool CPLX, int NTILE, int SWZ = 0, class F>
 __device__ __forceinline__ void acc_foreach(const Acc<CPLX, NTILE>& acc, F f) {
   using G = Geo<NTILE>;
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int wn = (w % G::WN) * 32;
 #pragma unroll
   for (int a = 0; a < G::BM; ++a)
 #pragma unroll
@@ -237,7 +253,7 @@ __device__ __forceinline__ void acc_foreach(const Acc<CPLX, NTILE>& acc, F f) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = block_row<NTILE, SWZ>(w, a) + (lane >> 4) + 4 * r;
-        const int n = wn + b * 16 + (lane & 15);
+        const int n = block_col<NTILE, SWZ>(w, b) + (lane & 15);
         cplx v{acc.re[a][b][r], CPLX ? acc.im[a][b][r] : 0.0};
         f(m, n, v);
       }
@@ -409,12 +425,14 @@ struct Stage2 {
 // triangular A operand on a 64-row tile (TriLive; the swizzled block rows),
 // those whose rows meet the chunk's k range in the nonzero triangle.
 struct AllLive {
-  static constexpr bool kAll = true, kSwz = false;
-  __device__ int operator()(int) const { return 3; }
+  static constexpr bool kAll = true;
+  static constexpr int kSwz = 0;
+  __device__ int operator()(int) const { return 15; }
 };
 template <bool LOWER>   // LOWER: A[m][k] = 0 for k > m; else A[m][k] = 0 for k < m
 struct TriLive {
-  static constexpr bool kAll = false, kSwz = true;
+  static constexpr bool kAll = false;
+  static constexpr int kSwz = 1;
   __device__ int operator()(int k0) const {
     static_assert(KC == 16, "a chunk spans one 16-row block");
     const int wr = (threadIdx.x >> 6) / Geo<64>::WN;
@@ -422,7 +440,23 @@ struct TriLive {
     const int mb0 = wr, mb1 = 3 - wr;
     const bool l0 = LOWER ? c <= mb0 : c >= mb0;
     const bool l1 = LOWER ? c <= mb1 : c >= mb1;
-    return __builtin_amdgcn_readfirstlane((l0 ? 1 : 0) | (l1 ? 2 : 0));
+    return __builtin_amdgcn_readfirstlane((l0 ? 3 : 0) | (l1 ? 12 : 0));   // both column blocks of a live row block
+  }
+};
+// A symmetric 64 x 64 result of which only the entries n >= m are needed:
+// the block pairs with column block >= row block (rows and columns swizzled,
+// so no wave has more than 3 of its 4 pairs).
+struct UpperLive {
+  static constexpr bool kAll = false;
+  static constexpr int kSwz = 3;
+  __device__ int operator()(int) const {
+    const int w = threadIdx.x >> 6;
+    const int wr = w / Geo<64>::WN, wc = w % Geo<64>::WN;
+    int mask = 0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        if ((b == 0 ? wc : 3 - wc) >= (a == 0 ? wr : 3 - wr)) mask |= 1 << (2 * a + b);
+    return __builtin_amdgcn_readfirstlane(mask);
   }
 };
 
@@ -432,9 +466,11 @@ __device__ __forceinline__ void run_chunk(Acc<CPLX, NTILE>& acc, const Stage<CPL
     mfma_chunk<CPLX, NTILE, SC>(acc, st);
   } else {
     const int m = lv(k0);
-    if (m == 3) mfma_chunk<CPLX, NTILE, SC, 3, LV::kSwz>(acc, st);
-    else if (m == 2) mfma_chunk<CPLX, NTILE, SC, 2, LV::kSwz>(acc, st);
-    else if (m == 1) mfma_chunk<CPLX, NTILE, SC, 1, LV::kSwz>(acc, st);
+    if (m == 15) mfma_chunk<CPLX, NTILE, SC, 15, LV::kSwz>(acc, st);
+    else if (m == 12) mfma_chunk<CPLX, NTILE, SC, 12, LV::kSwz>(acc, st);
+    else if (m == 3) mfma_chunk<CPLX, NTILE, SC, 3, LV::kSwz>(acc, st);
+    else if (m == 11) mfma_chunk<CPLX, NTILE, SC, 11, LV::kSwz>(acc, st);
+    else if (m == 10) mfma_chunk<CPLX, NTILE, SC, 10, LV::kSwz>(acc, st);
   }
 }
 
@@ -1119,6 +1155,8 @@ __global__ void PXS_LB(64) k_selinv_diag_partial(Src src) {
   const int kb = sp * (int)SPLIT_ROWS, ke = min(p.nb, kb + (int)SPLIT_ROWS);
   Acc<true, TM> acc;
   acc.zero();
+  // Z_pp is symmetric and stored by its lower triangle: only P[c][r], r >= c,
+  // is summed by k_selinv_diag_final, so the blocks below that are skipped
   gemm_pipe<true, TM, true>(
       acc, s, kb, ke,
       [&](int m, int kg) -> cplx {
@@ -1127,9 +1165,9 @@ __global__ void PXS_LB(64) k_selinv_diag_partial(Src src) {
       [&](int n, int kg) -> cplx {
         return ld_or_zero<true>(W, (int64_t)n * p.nb + kg, n < p.wp && kg < ke);
       },
-      KFast());
+      KFast(), NoScale(), UpperLive());
   double* out = part + 2 * (int64_t)sp * 64 * 64;
-  acc_foreach<true, TM>(acc, [&](int m, int n, cplx v) { st_elem<true>(out, (int64_t)m * 64 + n, v); });
+  acc_foreach<true, TM, UpperLive::kSwz>(acc, [&](int m, int n, cplx v) { st_elem<true>(out, (int64_t)m * 64 + n, v); });
 }
 
 // Z_pp = Linv^T D^{-1} Linv - sum of the partials, written over the diagonal block.
@@ -1180,10 +1218,10 @@ __global__ void __launch_bounds__(NTF) k_selinv_diag_final(Src src) {
 #pragma unroll
   for (int u = 0; u < NE; ++u) {
     const int cc = c0 + u * (NTF / 64);
-    if (cc >= wp || r >= wp) continue;
-    // sum_{k >= max(r, cc)} Linv[k][r] dinv[k] Linv[k][cc]
+    if (cc >= wp || r >= wp || r < cc) continue;   // the stored (lower) triangle
+    // sum_{k >= r} Linv[k][r] dinv[k] Linv[k][cc]
     cplx s{0.0, 0.0};
-    for (int k = max(r, cc); k < wp; ++k) {
+    for (int k = r; k < wp; ++k) {
       const cplx a{l_re[r][k], l_im[r][k]};
       const cplx b{l_re[cc][k], l_im[cc][k]};
       const cplx q = cmul(cmul(a, dinv[k]), b);
