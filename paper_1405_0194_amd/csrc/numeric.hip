@@ -421,9 +421,12 @@ struct Stage2 {
 // order per chunk.  gd(k), unless NoScale, returns a factor d_k applied to
 // column k of A on its way to the matrix cores (one load per k and chunk
 // instead of one per element); it must accept any k of the last chunk.
-// Which m-blocks of the wave take part in a chunk: all (AllLive), or, for a
-// triangular A operand on a 64-row tile (TriLive; the swizzled block rows),
-// those whose rows meet the chunk's k range in the nonzero triangle.
+// Which block pairs (a, b) of the wave take part in a chunk, as a mask of
+// bits 2a + b (evaluated per chunk, uniform over the wave): all (AllLive);
+// for a triangular A operand on a 64-row tile (TriLive, swizzled block rows),
+// both pairs of each row block whose rows meet the chunk's k range in the
+// nonzero triangle; for a symmetric 64 x 64 result of which one triangle is
+// used (UpperLive), the pairs on or above the block diagonal.
 struct AllLive {
   static constexpr bool kAll = true;
   static constexpr int kSwz = 0;
@@ -460,6 +463,9 @@ struct UpperLive {
   }
 };
 
+// The masks these functors return (15, 12, 3, 11, 10; 0 when no pair is
+// live) each have an instance below; a functor returning another mask would
+// skip its chunk, so a new one adds its masks here.
 template <bool CPLX, int NTILE, bool SC, class LV>
 __device__ __forceinline__ void run_chunk(Acc<CPLX, NTILE>& acc, const Stage<CPLX, NTILE>& st, LV lv, int k0) {
   if constexpr (LV::kAll) {
